@@ -1,0 +1,169 @@
+/*
+ * qldpc.h -- C ABI of the MI355X syndrome min-sum decoder library.
+ *
+ * The library decodes syndromes of quantum LDPC CSS codes with the
+ * normalized min-sum algorithm for syndrome-based decoding (Section 2,
+ * Algorithm 1 of "GPU-Accelerated Syndrome Decoding for Quantum LDPC Codes
+ * below the 63 us Latency Threshold").  Given one CSS side H (m checks,
+ * n variables) and a syndrome s = H e^T over GF(2) (Section 2, problem
+ * statement), it returns an estimate e_hat with H e_hat^T = s when the
+ * decoder converges.  One CSS side is one code object; decoding X and Z
+ * errors means two code objects (Section 2, CSS decoding).
+ *
+ * Conventions
+ *  - Every function returns qldpc_status and never aborts.  On failure,
+ *    qldpc_last_error() returns a message for the calling thread; out
+ *    parameters are written only on success.
+ *  - Host pointers are read during the call only.  Device pointers are
+ *    caller-owned device memory (e.g. PyTorch tensors) and must stay valid
+ *    until the work enqueued on `stream` has finished.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Decode calls
+ *    enqueue work and return without synchronising; they allocate nothing.
+ *    Argument checks are synchronous; device faults surface as
+ *    QLDPC_ERR_DEVICE from a later call or at stream synchronisation.
+ *  - Bit vectors (syndromes, error estimates) are packed per shot: bit i is
+ *    bit (i mod 32) of 32-bit word floor(i / 32), least significant first;
+ *    each shot's row is padded to whole words.  Pad bits are ignored on
+ *    input and written as zero.
+ *  - A code object is immutable after creation and may be used from any
+ *    host thread and stream concurrently.
+ */
+#ifndef QLDPC_H
+#define QLDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QLDPC_OK = 0,
+    QLDPC_ERR_INVALID_ARG = 1,   /* null pointer, bad size, malformed matrix  */
+    QLDPC_ERR_UNSUPPORTED = 2,   /* valid input this build has no kernel for  */
+    QLDPC_ERR_OUT_OF_MEMORY = 3, /* device allocation failed at create time   */
+    QLDPC_ERR_DEVICE = 4,        /* a HIP call failed                          */
+    QLDPC_ERR_CAPACITY = 5,      /* admission refused: over the memory budget  */
+    QLDPC_ERR_NOT_READY = 6      /* nothing to return yet                      */
+} qldpc_status;
+
+/* Thread-local message describing the last failure of this thread. */
+const char *qldpc_last_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t qldpc_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Code objects (Section 2: parity-check matrix H, Tanner graph S_v / S_c)   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct qldpc_code_s *qldpc_code;
+
+/* One CSS side.  H is given as host CSR: row r holds columns
+ * col_idx[row_ptr[r] .. row_ptr[r+1]-1], strictly increasing.  Edge e of
+ * the code is CSR position e (row-major, increasing column); it indexes the
+ * per-edge neural weights.
+ *
+ * Quasi-cyclic lift data: H is a base_m x base_n array of L x L blocks,
+ * base_exp[R * base_n + C] = a >= 0 for the circulant P^a
+ * (P^a[r][(r + a) mod L] = 1) or -1 for a zero block; then m = base_m * L
+ * and n = base_n * L, and the CSR must equal the expansion (checked).
+ * The device kernels use the lift: they need the block pattern of a
+ * lifted-product code LP(A, A*) with a 3 x 5 monomial base (H_Z or H_X
+ * side) and L in {16, 32, 64, 128}; other valid matrices are accepted by
+ * qldpc_code_create only if they match, else QLDPC_ERR_UNSUPPORTED. */
+typedef struct {
+    int32_t m, n;
+    const int32_t *row_ptr;   /* host, m + 1 entries, row_ptr[0] = 0 */
+    const int32_t *col_idx;   /* host, row_ptr[m] entries            */
+    int32_t lift_L;           /* 0 = no lift data                    */
+    int32_t base_m, base_n;
+    const int32_t *base_exp;  /* host, base_m * base_n entries       */
+} qldpc_code_desc;
+
+/* Validates the description, copies what the kernels need to `device`
+ * (allocated once, here), and returns a new code object.  Errors:
+ * INVALID_ARG (malformed CSR, lift data disagreeing with the CSR, a check of
+ * degree < 2), UNSUPPORTED (no kernel for this block pattern or L),
+ * OUT_OF_MEMORY, DEVICE. */
+qldpc_status qldpc_code_create(const qldpc_code_desc *desc, int32_t device, qldpc_code *out);
+
+/* Releases the code object and its device memory.  No work using the code
+ * may be pending.  NULL is accepted. */
+qldpc_status qldpc_code_destroy(qldpc_code code);
+
+/* m, n, number of edges, maximum check and variable degree (any out pointer
+ * may be NULL). */
+qldpc_status qldpc_code_info(qldpc_code code, int32_t *m, int32_t *n, int32_t *nnz,
+                             int32_t *max_dc, int32_t *max_dv);
+
+/* ------------------------------------------------------------------------ */
+/* Batched decoding (Algorithm 1)                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef enum {
+    QLDPC_F32 = 0,   /* FP32 messages; priors are float LLRs                 */
+    QLDPC_I8Q4 = 1   /* int8 saturating messages in [-127, 127]; priors are
+                        int8 Q4 fixed point (LLR * 16, see
+                        qldpc_quantize_prior); alpha must be num / 2^sh       */
+} qldpc_format;
+
+typedef enum {
+    QLDPC_FLOOD = 0,   /* all check nodes, then all variable nodes (Alg. 1)  */
+    QLDPC_LAYERED = 1  /* block row by block row, posterior updated in place */
+} qldpc_schedule;
+
+typedef enum {
+    QLDPC_PRIOR_PER_SHOT = 0,  /* priors [batch]: one LLR for every bit      */
+    QLDPC_PRIOR_PER_BIT = 1    /* priors [batch][n]                          */
+} qldpc_prior_mode;
+
+typedef enum {
+    QLDPC_LAYOUT_AUTO = 0,   /* tuned choice for (code, format, batch)       */
+    QLDPC_LAYOUT_WAVE = 1,   /* one wavefront decodes one shot (or 64 / L
+                                shots when L < 64); throughput layout        */
+    QLDPC_LAYOUT_BLOCK = 2   /* one workgroup of several wavefronts decodes
+                                one shot; latency layout                     */
+} qldpc_layout;
+
+typedef struct {
+    int32_t fmt;          /* qldpc_format                                    */
+    int32_t sched;        /* qldpc_schedule                                  */
+    float alpha;          /* normalisation factor in (0, 1] (Section 2)      */
+    int32_t max_iters;    /* I_max, 1 .. 255                                  */
+    int32_t early_stop;   /* 1: stop a shot once H e^(k) = s                 */
+    int32_t prior_mode;   /* qldpc_prior_mode                                */
+    int32_t layout;       /* qldpc_layout                                    */
+} qldpc_decode_params;
+
+/* Fills `p` with the defaults: F32, flooding, alpha 0.75, 32 iterations,
+ * early stop on, per-shot priors, automatic layout. */
+void qldpc_default_params(qldpc_decode_params *p);
+
+/* Decodes `batch` syndromes of one code.
+ *   syndromes  device uint32 [batch][ceil(m/32)]
+ *   priors     device float [batch] or [batch][n] (F32), int8 likewise (I8Q4)
+ *   errors     device uint32 [batch][ceil(n/32)], out: e_hat
+ *   converged  device uint8 [batch], out: 1 iff H e_hat = s at exit
+ *   iters_used device uint8 [batch], out, may be NULL: iterations executed
+ *   posterior  device float [batch][n], out, may be NULL: a-posteriori LLR Q
+ *              of the returned iteration (I8Q4: Q / 16)
+ * For each shot, the iteration k whose decision is returned is the first
+ * with H e^(k) = s when early_stop is set, else max_iters.  batch = 0 is a
+ * no-op.  Errors: INVALID_ARG, UNSUPPORTED (format/schedule/layout
+ * combination without a kernel), DEVICE. */
+qldpc_status qldpc_decode_batch(qldpc_code code, const qldpc_decode_params *params, int32_t batch,
+                                const uint32_t *syndromes, const void *priors, uint32_t *errors,
+                                uint8_t *converged, uint8_t *iters_used, float *posterior,
+                                void *stream);
+
+/* Host helper: int8 Q4 prior clamp(round-half-away-from-zero(16 * llr),
+ * -127, 127) for `count` values (host arrays). */
+qldpc_status qldpc_quantize_prior(const float *llr, int8_t *out, int64_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QLDPC_H */

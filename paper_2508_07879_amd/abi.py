@@ -1,0 +1,146 @@
+"""ctypes binding of the C ABI in include/qldpc.h (argument marshalling only).
+
+Each function keeps the C name and argument order.  Device buffers are
+passed as torch CUDA tensors (their data pointers); the stream defaults to
+torch's current stream.  Every decode step runs in the HIP library; if the
+library is missing this module raises on import.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqldpc.so")
+
+QLDPC_OK = 0
+QLDPC_ERR_INVALID_ARG = 1
+QLDPC_ERR_UNSUPPORTED = 2
+QLDPC_ERR_OUT_OF_MEMORY = 3
+QLDPC_ERR_DEVICE = 4
+QLDPC_ERR_CAPACITY = 5
+QLDPC_ERR_NOT_READY = 6
+
+QLDPC_F32, QLDPC_I8Q4 = 0, 1
+QLDPC_FLOOD, QLDPC_LAYERED = 0, 1
+QLDPC_PRIOR_PER_SHOT, QLDPC_PRIOR_PER_BIT = 0, 1
+QLDPC_LAYOUT_AUTO, QLDPC_LAYOUT_WAVE, QLDPC_LAYOUT_BLOCK = 0, 1, 2
+
+
+class QldpcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qldpc status {status}: {msg}")
+        self.status = status
+
+
+class qldpc_code_desc(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32),
+                ("row_ptr", C.POINTER(C.c_int32)), ("col_idx", C.POINTER(C.c_int32)),
+                ("lift_L", C.c_int32), ("base_m", C.c_int32), ("base_n", C.c_int32),
+                ("base_exp", C.POINTER(C.c_int32))]
+
+
+class qldpc_decode_params(C.Structure):
+    _fields_ = [("fmt", C.c_int32), ("sched", C.c_int32), ("alpha", C.c_float),
+                ("max_iters", C.c_int32), ("early_stop", C.c_int32),
+                ("prior_mode", C.c_int32), ("layout", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_07879_amd.build` "
+                          "(the decoder has no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "qldpc_last_error": ([], C.c_char_p),
+        "qldpc_version": ([], i32),
+        "qldpc_default_params": ([C.POINTER(qldpc_decode_params)], None),
+        "qldpc_quantize_prior": ([vp, vp, i64], i32),
+        "qldpc_code_create": ([C.POINTER(qldpc_code_desc), i32, C.POINTER(vp)], i32),
+        "qldpc_code_destroy": ([vp], i32),
+        "qldpc_code_info": ([vp, vp, vp, vp, vp, vp], i32),
+        "qldpc_decode_batch": ([vp, C.POINTER(qldpc_decode_params), i32, vp, vp, vp, vp, vp, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(st: int):
+    if st != QLDPC_OK:
+        raise QldpcError(st, lib.qldpc_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def qldpc_version() -> int:
+    return int(lib.qldpc_version())
+
+
+def qldpc_default_params() -> qldpc_decode_params:
+    p = qldpc_decode_params()
+    lib.qldpc_default_params(C.byref(p))
+    return p
+
+
+def qldpc_quantize_prior(llr: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(llr, dtype=np.float32)
+    out = np.empty(x.shape, np.int8)
+    _check(lib.qldpc_quantize_prior(x.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), x.size))
+    return out
+
+
+def qldpc_code_create(m: int, n: int, row_ptr, col_idx, lift_L: int = 0, base=None, device: int = 0):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    d = qldpc_code_desc()
+    d.m, d.n = int(m), int(n)
+    d.row_ptr = rp.ctypes.data_as(C.POINTER(C.c_int32))
+    d.col_idx = ci.ctypes.data_as(C.POINTER(C.c_int32))
+    d.lift_L = int(lift_L)
+    if base is not None:
+        be = np.ascontiguousarray(base, dtype=np.int32)
+        d.base_m, d.base_n = be.shape
+        d.base_exp = be.ctypes.data_as(C.POINTER(C.c_int32))
+    else:
+        d.base_m = d.base_n = 0
+        d.base_exp = None
+    h = C.c_void_p()
+    _check(lib.qldpc_code_create(C.byref(d), int(device), C.byref(h)))
+    return h
+
+
+def qldpc_code_destroy(h) -> None:
+    _check(lib.qldpc_code_destroy(h))
+
+
+def qldpc_code_info(h):
+    v = [C.c_int32() for _ in range(5)]
+    _check(lib.qldpc_code_info(h, *[C.byref(x) for x in v]))
+    return tuple(int(x.value) for x in v)
+
+
+def qldpc_decode_batch(h, params: qldpc_decode_params, batch: int, syndromes, priors, errors,
+                       converged, iters_used=None, posterior=None, stream=None) -> None:
+    _check(lib.qldpc_decode_batch(h, C.byref(params), int(batch), _ptr(syndromes), _ptr(priors),
+                                  _ptr(errors), _ptr(converged), _ptr(iters_used), _ptr(posterior),
+                                  _stream(stream)))

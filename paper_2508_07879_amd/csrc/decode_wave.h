@@ -1,0 +1,508 @@
+// Wavefront-per-shot min-sum decoder (throughput layout) for gfx950.
+//
+// Method: syndrome-based normalized min-sum, Section 2, Algorithm 1, in two
+// schedules: flooding (all check nodes, then all variable nodes) and
+// row-layered (block row by block row, a-posteriori values updated in place).
+//
+// Mapping.  The code is quasi-cyclic: a pattern of L x L circulants fixed at
+// compile time, with run-time shifts.  One wavefront decodes 64 / L shots
+// (L <= 64) or one shot (L = 128).  Lane t of a shot's segment owns row t of
+// every circulant: check (R, t) of each block row R and variable (C, t) of
+// each block column C.  Check (R, t) meets variable (C, (t + a) mod L)
+// through block (R, C) = P^a, so a check-side access is lane-contiguous and
+// a variable-side access is the same row rotated by a: both are free of LDS
+// bank conflicts, and every address offset except the rotation is constant.
+//
+// LDS state per wave:
+//   flooding: msg[(R * 8 + j) * ROW + lane], one entry per edge in CSR order,
+//             holding q before a check pass and r after it (each entry is
+//             read and written by exactly one lane per pass: in place);
+//   layered:  r per edge (same layout) and the posterior Q[C * ROW + lane].
+// ROW = 64 lanes (x2 circulant rows per lane at L = 128).
+//
+// Decisions and the syndrome test.  e_n = [Q_n < 0] of block column C is a
+// 64-bit ballot.  Block row R accumulates s_R xor rot(e_C, a) over its 8
+// blocks in scalar registers (a segment-wise rotation of the ballot by the
+// circulant shift); the shot has converged when every accumulator is zero.
+//
+// Numerics.  FP32 follows a fixed order: excluded sums left to right from
+// gamma_n in increasing check index, alpha * min rounded once, no
+// contraction.  Priors are canonicalised with + 0.0f so no message is -0.0;
+// the raw sign bit of q is then [q < 0] and the sign product is an XOR of
+// sign bits.  int8 (Q4 priors): |q| in [0, 127], r = sign * ((num * min) >>
+// sh), integer sums exact, q saturated to [-127, 127].
+#pragma once
+#include <stdint.h>
+
+#include "kernels.h"
+#include "shapes.h"
+
+namespace qldpc {
+
+template <class S, int L>
+struct Geo {
+    static constexpr int SEG = L < 64 ? L : 64;      // lanes per shot
+    static constexpr int SPW = 64 / SEG;             // shots per wave
+    static constexpr int PPL = L > 64 ? L / 64 : 1;  // circulant rows per lane
+    static constexpr int ROW = 64 * PPL;             // entries per slot row
+    static constexpr int N = S::NB * L;
+    static constexpr int SW = (S::MB * L + 31) / 32;  // syndrome words per shot
+    static constexpr int EW = (S::NB * L + 31) / 32;  // error words per shot
+    static constexpr uint64_t SEGMASK = L >= 64 ? ~0ull : ((1ull << L) - 1);
+};
+
+template <int FMT> struct Fmt;
+template <> struct Fmt<0> { using msg_t = float; using q_t = float; using prior_t = float; };
+template <> struct Fmt<1> { using msg_t = int8_t; using q_t = int16_t; using prior_t = int8_t; };
+
+template <class S, int L, int FMT, int SCHED>
+struct WaveLds {
+    using G = Geo<S, L>;
+    using msg_t = typename Fmt<FMT>::msg_t;
+    using q_t = typename Fmt<FMT>::q_t;
+    static constexpr int MSG = S::SLOTS * G::ROW;
+    static constexpr int QN = SCHED == 1 ? S::NB * G::ROW : 0;
+    static constexpr size_t msg_bytes = MSG * sizeof(msg_t);
+    static constexpr size_t q_off = (msg_bytes + 15) & ~size_t(15);
+    static constexpr size_t e_off = (q_off + QN * sizeof(q_t) + 15) & ~size_t(15);
+    static constexpr size_t bytes = e_off + G::SPW * G::EW * 4;
+};
+
+namespace wave {
+
+// Rotate every L-bit segment of a ballot right by s: bit t of a segment
+// becomes bit (t + s) mod L of the same segment.  `low` has the low L - s
+// bits of every segment set.
+template <int L>
+__device__ __forceinline__ uint64_t seg_rotr(uint64_t m, uint32_t s, uint64_t low) {
+    if constexpr (L == 64) {
+        return (m >> s) | (m << ((64u - s) & 63u));
+    } else {
+        return ((m >> s) & low) | ((m << (L - s)) & ~low);
+    }
+}
+
+// 128-bit rotate right (L = 128: positions 0..63 in lo, 64..127 in hi).
+__device__ __forceinline__ void rotr128(uint64_t lo, uint64_t hi, uint32_t s, uint64_t &olo,
+                                        uint64_t &ohi) {
+    if (s >= 64u) {
+        const uint64_t t = lo;
+        lo = hi;
+        hi = t;
+        s -= 64u;
+    }
+    olo = (lo >> s) | ((hi << 1) << (63u - s));
+    ohi = (hi >> s) | ((lo << 1) << (63u - s));
+}
+
+__device__ __forceinline__ uint32_t fbits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ float ubits(uint32_t x) { return __uint_as_float(x); }
+__device__ __forceinline__ uint64_t ballot(bool b) { return __ballot(b); }
+
+// Position inside a slot row of the entry that variable position
+// (lane + 64 h) reaches through a block of shift s (check = var - s).
+template <int L>
+__device__ __forceinline__ int vn_index(int lane, int h, uint32_t s) {
+    if constexpr (L <= 64) {
+        return (int)(((uint32_t)lane - s) & (uint32_t)(L - 1)) | (lane & ~(L - 1));
+    } else {
+        return (int)(((uint32_t)(lane + 64 * h) - s) & (uint32_t)(L - 1));
+    }
+}
+
+// Position inside a block-column row of the variable that check position
+// (lane + 64 h) reaches through a block of shift s (var = check + s).
+template <int L>
+__device__ __forceinline__ int cn_index(int lane, int h, uint32_t s) {
+    if constexpr (L <= 64) {
+        return (int)(((uint32_t)lane + s) & (uint32_t)(L - 1)) | (lane & ~(L - 1));
+    } else {
+        return (int)(((uint32_t)(lane + 64 * h) + s) & (uint32_t)(L - 1));
+    }
+}
+
+// ---- check-node rule, FP32 (Algorithm 1): r_j = (-1)^{s + sum_{i != j} neg_i}
+//      * fl(alpha * min_{i != j} |q_i|).  P carries s in bit 31 on entry.
+template <int DC>
+__device__ __forceinline__ void cn_f32(float (&v)[DC], uint32_t P, float alpha) {
+    float m1 = fminf(fabsf(v[0]), fabsf(v[1]));
+    float m2 = fmaxf(fabsf(v[0]), fabsf(v[1]));
+#pragma unroll
+    for (int j = 2; j < DC; ++j) {
+        m2 = __builtin_amdgcn_fmed3f(m1, m2, fabsf(v[j]));
+        m1 = fminf(m1, fabsf(v[j]));
+    }
+#pragma unroll
+    for (int j = 0; j < DC; ++j) P ^= fbits(v[j]);
+    const float A1 = alpha * m1;
+    const float A2 = alpha * m2;
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        // |q_j| == min1: j is the (or a tied) minimum; the excluded minimum is
+        // min2 (equal to min1 on a tie).
+        const float mag = (fabsf(v[j]) == m1) ? A2 : A1;
+        v[j] = ubits(fbits(mag) | ((P ^ fbits(v[j])) & 0x80000000u));
+    }
+}
+
+// ---- check-node rule, int8: magnitudes in [0, 127], alpha = num / 2^sh
+//      applied to the magnitude and rounded down, before the sign.
+template <int DC>
+__device__ __forceinline__ void cn_i8(int (&v)[DC], uint32_t P, int num, int sh) {
+    int a[DC];
+#pragma unroll
+    for (int j = 0; j < DC; ++j) a[j] = v[j] < 0 ? -v[j] : v[j];
+    int m1 = min(a[0], a[1]);
+    int m2 = max(a[0], a[1]);
+#pragma unroll
+    for (int j = 2; j < DC; ++j) {
+        m2 = max(m1, min(m2, a[j]));   // med3(m1, m2, a_j) for m1 <= m2
+        m1 = min(m1, a[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < DC; ++j) P ^= (uint32_t)v[j];
+    const int A1 = (num * m1) >> sh;
+    const int A2 = (num * m2) >> sh;
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        const int mag = (a[j] == m1) ? A2 : A1;
+        v[j] = ((int)(P ^ (uint32_t)v[j]) < 0) ? -mag : mag;
+    }
+}
+
+__device__ __forceinline__ int sat127(int x) { return min(127, max(-127, x)); }
+
+}  // namespace wave
+
+// ---------------------------------------------------------------------------
+// The decoder body: decodes the 64 / L (or 1) shots starting at shot_base.
+// `lds` points to WaveLds<...>::bytes of this wave's LDS.
+// ---------------------------------------------------------------------------
+template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST>
+__device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *__restrict__ code,
+                                            long shot_base, int64_t limit, unsigned char *lds) {
+    using namespace wave;
+    using G = Geo<S, L>;
+    using Lay = WaveLds<S, L, FMT, SCHED>;
+    using msg_t = typename Fmt<FMT>::msg_t;
+    using q_t = typename Fmt<FMT>::q_t;
+    using prior_t = typename Fmt<FMT>::prior_t;
+    using acc_t = typename std::conditional<FMT == 0, float, int>::type;
+    constexpr int MB = S::MB, NB = S::NB, DC = S::DC, PPL = G::PPL, ROW = G::ROW;
+
+    msg_t *msg = reinterpret_cast<msg_t *>(lds);
+    q_t *Qs = reinterpret_cast<q_t *>(lds + Lay::q_off);
+    uint32_t *ebuf = reinterpret_cast<uint32_t *>(lds + Lay::e_off);
+
+    const int lane = threadIdx.x & 63;
+    const int g = lane / G::SEG;
+    const int p = lane % G::SEG;
+    const long shot = shot_base + g;
+    const bool valid = shot < limit;
+
+    // Syndrome bits of this lane's checks: bit R of sb[h] = s of check R*L + p + 64h.
+    uint32_t sb[PPL];
+#pragma unroll
+    for (int h = 0; h < PPL; ++h) {
+        sb[h] = 0;
+        if (valid) {
+#pragma unroll
+            for (int R = 0; R < MB; ++R) {
+                const int m = R * L + p + 64 * h;
+                const uint32_t w = a.syn[shot * G::SW + (m >> 5)];
+                sb[h] |= ((w >> (m & 31)) & 1u) << R;
+            }
+        }
+    }
+    // Priors (FP32 canonicalised so that no message is -0.0).
+    acc_t gam[PER_BIT ? NB * PPL : 1];
+    {
+        const prior_t *pr = static_cast<const prior_t *>(a.prior);
+        if constexpr (PER_BIT) {
+#pragma unroll
+            for (int C = 0; C < NB; ++C)
+#pragma unroll
+                for (int h = 0; h < PPL; ++h) {
+                    acc_t v = valid ? (acc_t)pr[shot * G::N + C * L + p + 64 * h] : (acc_t)1;
+                    if constexpr (FMT == 0) v = v + 0.0f;
+                    gam[C * PPL + h] = v;
+                }
+        } else {
+            acc_t v = valid ? (acc_t)pr[shot] : (acc_t)1;
+            if constexpr (FMT == 0) v = v + 0.0f;
+            gam[0] = v;
+        }
+    }
+    auto gamma_of = [&](int C, int h) -> acc_t { return PER_BIT ? gam[C * PPL + h] : gam[0]; };
+
+    // Initial state.  Flooding: q^(0) = gamma on every edge.  Layered: r = 0,
+    // Q = gamma.
+    if constexpr (SCHED == 0) {
+        static_for<0, NB>([&](auto Cc) {
+            constexpr int C = decltype(Cc)::value;
+            static_for<0, S::T.col_deg[C]>([&](auto Ii) {
+                constexpr int i = decltype(Ii)::value;
+                constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
+                const uint32_t s = (uint32_t)code->shift[slot];
+#pragma unroll
+                for (int h = 0; h < PPL; ++h)
+                    msg[slot * ROW + vn_index<L>(lane, h, s)] = (msg_t)gamma_of(C, h);
+            });
+        });
+    } else {
+#pragma unroll
+        for (int sl = 0; sl < S::SLOTS; ++sl)
+#pragma unroll
+            for (int h = 0; h < PPL; ++h) msg[sl * ROW + lane + 64 * h] = (msg_t)0;
+#pragma unroll
+        for (int C = 0; C < NB; ++C)
+#pragma unroll
+            for (int h = 0; h < PPL; ++h) Qs[C * ROW + lane + 64 * h] = (q_t)gamma_of(C, h);
+    }
+
+    acc_t Qr[POST ? NB * PPL : 1];
+    uint64_t eb[PPL];
+    bool done = !valid;
+
+    for (int k = 1; k <= a.max_iters; ++k) {
+        __builtin_amdgcn_wave_barrier();
+        uint64_t acc[MB][PPL];
+#pragma unroll
+        for (int R = 0; R < MB; ++R)
+#pragma unroll
+            for (int h = 0; h < PPL; ++h) acc[R][h] = ballot(((sb[h] >> R) & 1u) != 0);
+#pragma unroll
+        for (int h = 0; h < PPL; ++h) eb[h] = 0;
+
+        if constexpr (SCHED == 0) {
+            // ---------------- check-node pass --------------------------------
+#pragma unroll
+            for (int R = 0; R < MB; ++R) {
+#pragma unroll
+                for (int h = 0; h < PPL; ++h) {
+                    const uint32_t P = sb[h] << (31 - R);
+                    if constexpr (FMT == 0) {
+                        float v[DC];
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) v[j] = msg[(R * DC + j) * ROW + lane + 64 * h];
+                        cn_f32<DC>(v, P, a.alpha);
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) msg[(R * DC + j) * ROW + lane + 64 * h] = v[j];
+                    } else {
+                        int v[DC];
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) v[j] = msg[(R * DC + j) * ROW + lane + 64 * h];
+                        cn_i8<DC>(v, P, a.alpha_num, a.alpha_shift);
+#pragma unroll
+                        for (int j = 0; j < DC; ++j)
+                            msg[(R * DC + j) * ROW + lane + 64 * h] = (msg_t)v[j];
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            // ---------------- layers: one block row at a time ----------------
+            static_for<0, MB>([&](auto Rc) {
+                constexpr int R = decltype(Rc)::value;
+#pragma unroll
+                for (int h = 0; h < PPL; ++h) {
+                    const uint32_t P = sb[h] << (31 - R);
+                    int qi[DC];
+                    acc_t v[DC], rold[DC];
+                    static_for<0, DC>([&](auto Jc) {
+                        constexpr int j = decltype(Jc)::value;
+                        constexpr int C = S::T.slot_bc[R][j];
+                        const uint32_t s = (uint32_t)code->shift[R * DC + j];
+                        qi[j] = C * ROW + cn_index<L>(lane, h, s);
+                        rold[j] = (acc_t)msg[(R * DC + j) * ROW + lane + 64 * h];
+                    });
+                    if constexpr (FMT == 0) {
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) v[j] = Qs[qi[j]] - rold[j];
+                        float c[DC];
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) c[j] = v[j];
+                        cn_f32<DC>(c, P, a.alpha);
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) {
+                            Qs[qi[j]] = v[j] + c[j];
+                            msg[(R * DC + j) * ROW + lane + 64 * h] = c[j];
+                        }
+                    } else {
+                        int c[DC];
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) {
+                            v[j] = (int)Qs[qi[j]] - rold[j];     // exact
+                            c[j] = sat127(v[j]);                 // check-node input
+                        }
+                        cn_i8<DC>(c, P, a.alpha_num, a.alpha_shift);
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) {
+                            Qs[qi[j]] = (q_t)(v[j] + c[j]);
+                            msg[(R * DC + j) * ROW + lane + 64 * h] = (msg_t)c[j];
+                        }
+                    }
+                }
+            });
+            __builtin_amdgcn_wave_barrier();
+        }
+
+        // ---------------- variable nodes, a posteriori, decision -------------
+        static_for<0, NB>([&](auto Cc) {
+            constexpr int C = decltype(Cc)::value;
+            constexpr int d = S::T.col_deg[C];
+            uint64_t mask[PPL];
+#pragma unroll
+            for (int h = 0; h < PPL; ++h) {
+                acc_t Q;
+                if constexpr (SCHED == 0) {
+                    acc_t r[d];
+                    int idx[d];
+                    static_for<0, d>([&](auto Ii) {
+                        constexpr int i = decltype(Ii)::value;
+                        constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
+                        idx[i] = slot * ROW + vn_index<L>(lane, h, (uint32_t)code->shift[slot]);
+                        r[i] = (acc_t)msg[idx[i]];
+                    });
+                    if constexpr (FMT == 0) {
+                        // prefix sums from gamma in increasing check order; the
+                        // excluded sum of edge i continues the prefix before i
+                        float pre[d + 1];
+                        pre[0] = gamma_of(C, h);
+#pragma unroll
+                        for (int i = 0; i < d; ++i) pre[i + 1] = pre[i] + r[i];
+#pragma unroll
+                        for (int i = 0; i < d; ++i) {
+                            float q = pre[i];
+#pragma unroll
+                            for (int j = i + 1; j < d; ++j) q = q + r[j];
+                            msg[idx[i]] = q;
+                        }
+                        Q = pre[d];
+                    } else {
+                        int sum = gamma_of(C, h);
+#pragma unroll
+                        for (int i = 0; i < d; ++i) sum += r[i];
+#pragma unroll
+                        for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
+                        Q = sum;
+                    }
+                } else {
+                    Q = (acc_t)Qs[C * ROW + lane + 64 * h];
+                }
+                if constexpr (POST) Qr[C * PPL + h] = Q;
+                const bool e = Q < (acc_t)0;
+                eb[h] |= (uint64_t)e << C;
+                mask[h] = ballot(e);
+            }
+            // syndrome accumulation in scalar registers
+            static_for<0, d>([&](auto Ii) {
+                constexpr int i = decltype(Ii)::value;
+                constexpr int R = S::T.col_R[C][i];
+                constexpr int slot = R * DC + S::T.col_j[C][i];
+                const uint32_t s = (uint32_t)code->shift[slot];
+                if constexpr (L <= 64) {
+                    acc[R][0] ^= seg_rotr<L>(mask[0], s, code->lowmask[slot]);
+                } else {
+                    uint64_t lo, hi;
+                    rotr128(mask[0], mask[PPL - 1], s, lo, hi);
+                    acc[R][0] ^= lo;
+                    acc[R][PPL - 1] ^= hi;
+                }
+            });
+        });
+
+        // ---------------- stopping rule --------------------------------------
+        uint64_t uns[PPL];
+#pragma unroll
+        for (int h = 0; h < PPL; ++h) {
+            uns[h] = 0;
+#pragma unroll
+            for (int R = 0; R < MB; ++R) uns[h] |= acc[R][h];
+        }
+        bool my_unsat;
+        if constexpr (L < 64) {
+            my_unsat = ((uns[0] >> (g * L)) & G::SEGMASK) != 0;
+        } else if constexpr (L == 64) {
+            my_unsat = uns[0] != 0;
+        } else {
+            my_unsat = (uns[0] | uns[PPL - 1]) != 0;
+        }
+        const bool conv_now = !my_unsat;
+        const bool emit_me = !done && ((a.early_stop && conv_now) || k == a.max_iters);
+        if (ballot(emit_me)) {
+            // stage the packed decisions of every shot of the wave in LDS
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int C = 0; C < NB; ++C) {
+#pragma unroll
+                for (int h = 0; h < PPL; ++h) {
+                    const uint64_t m = ballot(((eb[h] >> C) & 1ull) != 0);
+                    if constexpr (L == 16) {
+                        if (lane < 4)
+                            reinterpret_cast<uint16_t *>(ebuf)[lane * G::EW * 2 + C] =
+                                (uint16_t)(m >> (16 * lane));
+                    } else if constexpr (L == 32) {
+                        if (lane < 2) ebuf[lane * G::EW + C] = (uint32_t)(m >> (32 * lane));
+                    } else if constexpr (L == 64) {
+                        if (lane < 2) ebuf[2 * C + lane] = (uint32_t)(m >> (32 * lane));
+                    } else {
+                        if (lane < 2) ebuf[4 * C + 2 * h + lane] = (uint32_t)(m >> (32 * lane));
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (emit_me) {
+                for (int w = p; w < G::EW; w += G::SEG) a.err[shot * G::EW + w] = ebuf[g * G::EW + w];
+                if (p == 0) {
+                    a.conv[shot] = conv_now ? 1 : 0;
+                    if (a.iters) a.iters[shot] = (uint8_t)k;
+                }
+                if constexpr (POST) {
+#pragma unroll
+                    for (int C = 0; C < NB; ++C)
+#pragma unroll
+                        for (int h = 0; h < PPL; ++h) {
+                            float qv;
+                            if constexpr (FMT == 0) qv = Qr[C * PPL + h];
+                            else qv = (float)Qr[C * PPL + h] * 0.0625f;
+                            a.post[shot * G::N + C * L + p + 64 * h] = qv;
+                        }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        done = done || emit_me;
+        if (ballot(!done) == 0) break;
+    }
+}
+
+// One wave per workgroup; grid = ceil(batch / shots-per-wave).
+template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST>
+__global__ __launch_bounds__(64) void k_wave(const DecodeArgs a) {
+    using Lay = WaveLds<S, L, FMT, SCHED>;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
+    wave_decode<S, L, FMT, SCHED, PER_BIT, POST>(a, a.code, (long)blockIdx.x * Geo<S, L>::SPW,
+                                                 a.batch, lds);
+}
+
+template <class S, int L, int FMT, int SCHED, bool PB, bool PO>
+hipError_t launch_wave_one(const DecodeArgs &a, hipStream_t st) {
+    using G = Geo<S, L>;
+    const unsigned grid = (unsigned)((a.batch + G::SPW - 1) / G::SPW);
+    hipLaunchKernelGGL((k_wave<S, L, FMT, SCHED, PB, PO>), dim3(grid), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+template <class S, int L, int FMT, int SCHED>
+hipError_t launch_wave(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
+    if (k.per_bit)
+        return k.post ? launch_wave_one<S, L, FMT, SCHED, true, true>(a, st)
+                      : launch_wave_one<S, L, FMT, SCHED, true, false>(a, st);
+    return k.post ? launch_wave_one<S, L, FMT, SCHED, false, true>(a, st)
+                  : launch_wave_one<S, L, FMT, SCHED, false, false>(a, st);
+}
+
+}  // namespace qldpc

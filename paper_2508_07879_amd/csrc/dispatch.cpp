@@ -1,0 +1,24 @@
+// Kernel selection for a decode call.
+#include "kernels.h"
+
+namespace qldpc {
+
+hipError_t launch_wave_L16(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_wave_L32(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_wave_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_wave_L128(const LaunchKey &, const DecodeArgs &, hipStream_t);
+
+hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t stream) {
+    if (k.layout == 1) {
+        switch (k.L) {
+            case 16: return launch_wave_L16(k, a, stream);
+            case 32: return launch_wave_L32(k, a, stream);
+            case 64: return launch_wave_L64(k, a, stream);
+            case 128: return launch_wave_L128(k, a, stream);
+            default: break;
+        }
+    }
+    return hipErrorNotSupported;
+}
+
+}  // namespace qldpc

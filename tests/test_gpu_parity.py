@@ -1,0 +1,170 @@
+"""Device decoder (through the C ABI) against the CPU oracle.
+
+The bar: identical hard decisions, convergence flags and iteration counts
+per shot; FP32 posteriors within 1e-5 relative error
+(|dQ| <= 1e-5 * max(|Q_oracle|, |gamma|)); int8 posteriors bit-exact.
+Inputs are the seeded workloads: lifted-product codes LP(A, A*) with a 3x5
+monomial base, iid X flips, H_Z syndromes.
+"""
+import numpy as np
+import pytest
+
+from workload import lp, noise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2508_07879_amd import Decoder, abi  # noqa: E402
+
+from gpu_util import assert_parity, gpu_decode, oracle_decode  # noqa: E402
+
+_codes = {}
+
+
+def code(L):
+    if L not in _codes:
+        c = lp.lp_code(L)
+        _codes[L] = (c, c.hz.dense(), Decoder(c.hz))
+    return _codes[L]
+
+
+def run_case(L, shots, p, fmt=0, sched=0, per_bit=False, seed=7, max_iters=32, early_stop=True,
+             alpha=0.75, syn=None):
+    c, H, dec = code(L)
+    b = noise.Batch(c.hz, seed, np.arange(shots), p)
+    s = b.s if syn is None else syn
+    if fmt == 0:
+        prior = b.prior_bits() if per_bit else b.gamma
+        if per_bit:
+            # per-bit jitter so that every bit has its own prior
+            j = noise.rng.uniform(seed, noise.rng.DOMAIN_PRIOR, np.arange(shots)[:, None],
+                                  np.arange(c.n)[None, :])
+            prior = (prior * (0.5 + j)).astype(np.float32)
+        scale = prior if per_bit else b.gamma[:, None]
+    else:
+        q = b.gamma_q4()
+        if per_bit:
+            j = noise.rng.uniform(seed, noise.rng.DOMAIN_PRIOR, np.arange(shots)[:, None],
+                                  np.arange(c.n)[None, :])
+            q = np.clip(np.round(q[:, None] * (0.5 + j)), -127, 127).astype(np.int8)
+        prior = q
+        scale = None
+    g = gpu_decode(dec, s, prior, fmt=fmt, sched=sched, max_iters=max_iters, early_stop=early_stop,
+                   per_bit=per_bit, alpha=alpha)
+    o = oracle_decode(H, s, prior, fmt=fmt, sched=sched, max_iters=max_iters, early_stop=early_stop,
+                      layer_size=L, alpha=alpha)
+    assert_parity(g, o, scale, fmt, tag=f"L={L} p={p} fmt={fmt} sched={sched} pb={per_bit}")
+    return g, o
+
+
+def test_config0_fp32_flood_1000_shots():
+    """L = 16 (N = 544), p = 0.03, alpha 0.75, flooding, 32 iterations, FP32."""
+    g, o = run_case(16, 1000, 0.03)
+    assert o.converged.mean() > 0.9
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("sched", [0, 1])
+@pytest.mark.parametrize("p", [0.01, 0.03, 0.05])
+def test_L64_formats_and_schedules(fmt, sched, p):
+    run_case(64, 192, p, fmt=fmt, sched=sched, seed=11)
+
+
+@pytest.mark.parametrize("L", [16, 32, 64, 128])
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("sched", [0, 1])
+def test_all_lifts(L, fmt, sched):
+    # shot counts leave a ragged last wave for L < 64
+    run_case(L, 67, 0.05, fmt=fmt, sched=sched, seed=13)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("L", [16, 64, 128])
+def test_per_bit_priors(fmt, L):
+    run_case(L, 45, 0.04, fmt=fmt, per_bit=True, seed=17)
+    run_case(L, 45, 0.04, fmt=fmt, sched=1, per_bit=True, seed=18)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_fixed_iterations_and_one_iteration(fmt):
+    run_case(64, 64, 0.05, fmt=fmt, max_iters=10, early_stop=False, seed=19)
+    g, o = run_case(64, 64, 0.05, fmt=fmt, max_iters=1, seed=20)
+    assert np.all(g[2] == 1)
+
+
+def test_alpha_one_and_half():
+    run_case(32, 64, 0.05, alpha=1.0, seed=21)
+    run_case(32, 64, 0.05, fmt=1, alpha=0.5, seed=22)
+
+
+def test_zero_and_inconsistent_syndromes():
+    c, H, dec = code(64)
+    z = np.zeros((5, c.hz.m), np.uint8)
+    g, o = run_case(64, 5, 0.03, syn=z)
+    assert np.all(g[2] == 1) and np.all(g[1] == 1) and not g[0].any()
+    rnd = noise.random_syndromes(23, np.arange(40), c.hz.m)
+    g, o = run_case(64, 40, 0.03, syn=rnd, max_iters=12)
+    # H_Z has rank m - 8 for this code, so almost every random syndrome is
+    # inconsistent and can never converge
+    assert g[1].sum() <= 2
+
+
+def test_single_shot_and_empty_batch():
+    run_case(64, 1, 0.05, seed=24)
+    run_case(16, 1, 0.05, seed=25)
+    c, H, dec = code(64)
+    err, conv, it, post = dec.outputs(0)
+    dec.decode(torch.zeros((0, dec.syn_words), dtype=torch.int32, device="cuda"),
+               torch.zeros((0,), dtype=torch.float32, device="cuda"), out=(err, conv, it, post))
+    torch.cuda.synchronize()
+
+
+def test_deterministic_and_order_independent():
+    c, H, dec = code(64)
+    b = noise.Batch(c.hz, 26, np.arange(128), 0.05)
+    g1 = gpu_decode(dec, b.s, b.gamma)
+    g2 = gpu_decode(dec, b.s, b.gamma)
+    perm = np.random.default_rng(0).permutation(128)
+    g3 = gpu_decode(dec, b.s[perm], b.gamma[perm])
+    for a_, b_ in zip(g1, g2):
+        assert np.array_equal(a_, b_)
+    for a_, b_ in zip(g1, g3):
+        assert np.array_equal(a_[perm], b_)
+
+
+def test_invalid_arguments():
+    c, H, dec = code(64)
+    p = dec.params(max_iters=0)
+    err, conv, it, post = dec.outputs(4)
+    syn = torch.zeros((4, dec.syn_words), dtype=torch.int32, device="cuda")
+    pr = torch.ones(4, dtype=torch.float32, device="cuda")
+    with pytest.raises(abi.QldpcError) as ei:
+        abi.qldpc_decode_batch(dec.handle, p, 4, syn, pr, err, conv, it, None)
+    assert ei.value.status == abi.QLDPC_ERR_INVALID_ARG
+    p = dec.params(fmt=abi.QLDPC_I8Q4, alpha=0.7)
+    with pytest.raises(abi.QldpcError) as ei:
+        abi.qldpc_decode_batch(dec.handle, p, 4, syn, pr, err, conv, it, None)
+    assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("fmt,sched", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_full_batch_sampled(fmt, sched):
+    """65536 shots at L = 64, p = 0.05, as the benchmark launches them; the
+    oracle re-decodes a sample of shots one by one, and every converged shot
+    must reproduce its syndrome."""
+    c, H, dec = code(64)
+    B = 65536
+    b = noise.Batch(c.hz, 1000 + fmt + 2 * sched, np.arange(B), 0.05)
+    prior = b.gamma if fmt == 0 else b.gamma_q4()
+    g = gpu_decode(dec, b.s, prior, fmt=fmt, sched=sched, posterior=False)
+    e, conv, it, _ = g
+    ok = conv == 1
+    assert np.array_equal(noise.syndromes(c.hz, e[ok]), b.s[ok])
+    assert ok.mean() > 0.5
+    idx = np.unique(np.concatenate([np.arange(0, B, 1024), [B - 1], np.nonzero(~ok)[0][:16]]))
+    o = oracle_decode(H, b.s[idx], prior[idx], fmt=fmt, sched=sched, layer_size=64)
+    assert np.array_equal(e[idx], o.e) and np.array_equal(conv[idx], o.converged)
+    assert np.array_equal(it[idx], o.iters)
