@@ -28,6 +28,9 @@ sys.path.insert(0, ROOT)
 METRIC = "syndromes decoded/sec + p50/p99 latency µs (N=2176, 32 iters) at equal logical error rate"
 P_LIST = (0.01, 0.03, 0.05)
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak of MI355X in lane-operations: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz, one non-packed operation per lane per clock.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def edge_model_bytes(E: int, bytes_per_msg: int) -> int:
@@ -37,6 +40,29 @@ def edge_model_bytes(E: int, bytes_per_msg: int) -> int:
     return 4 * E * bytes_per_msg
 
 
+def alu_ops_per_shot_iter(side) -> int:
+    """Algorithmic lane-operations of one min-sum iteration: 9 per edge in
+    the check rule (magnitude, running min1/min2, sign parity, select,
+    scale, sign) and d^2 + d per variable of degree d (the d excluded sums of
+    d - 1 terms, the posterior, the decision and the d message writes)."""
+    deg = np.bincount(side.col_idx, minlength=side.n)
+    return int(9 * side.nnz + np.sum(deg * deg + deg))
+
+
+def recorded_traffic(kernel_sources):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_wave_f32_flood_L64.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return t["bytes_per_launch"] if h.hexdigest()[:16] == t["source_sha"] else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,10 +70,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--L", type=int, default=64)
-    ap.add_argument("--cpu-shots", type=int, default=4096, help="oracle sample per noise rate")
+    ap.add_argument("--cpu-shots", type=int, default=8192, help="oracle sample per noise rate")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--seed", type=int, default=20250807)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run one plain device copy of MIB MiB (a known-size "
+                         "kernel for scaling HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -115,6 +144,17 @@ def main():
     per_launch_bytes = np.array([it * edge_model_bytes(E, 4) + B * io_bytes for it in its], dtype=np.float64)
     mean_kernel_ms = kms.mean(axis=0)                     # per noise rate
     achieved_gbs = float(per_launch_bytes.sum() / (mean_kernel_ms.sum() * 1e-3) / 1e9)
+    ops_si = alu_ops_per_shot_iter(side)
+    shot_iters_per_s = float(sum(its) / (mean_kernel_ms.sum() * 1e-3))
+    achieved_tops = shot_iters_per_s * ops_si / 1e12
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # logical error rate of the timed decodes (failure = not converged or a
     # logical flip of the residual)
@@ -180,15 +220,22 @@ def main():
             "schedule": "flooding", "layout": "wavefront per shot, messages in LDS",
         },
         "roofline": {
-            "bound": "hbm",
-            "achieved": achieved_gbs,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
-            "model": "edge model: 4*E*4 B per executed shot-iteration + 398 B I/O per shot, "
-                     "per launch / mean launch time (HIP events on the decode stream)",
+            "bound": "alu",
+            "achieved": achieved_tops,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "Tops/s",
+            "frac": achieved_tops / VALU_PEAK_TOPS,
+            "traffic": recorded_traffic(None) if args.L == 64 and B == 65536 else None,
+            "model": f"{ops_si} lane-ops per executed shot-iteration (9 per edge + d^2+d per "
+                     "variable) x executed shot-iterations per launch / mean launch time (HIP "
+                     "events on the decode stream); peak = 256 CU x 64 lanes x 2.4 GHz",
             "kernel_ms_per_launch": {str(p): float(m) for p, m in zip(P_LIST, mean_kernel_ms)},
+            "shot_iters_per_s": shot_iters_per_s,
+        },
+        "hbm_edge_model": {
+            "achieved_GBps": achieved_gbs, "peak_GBps": HBM_PEAK_GBS, "frac": achieved_gbs / HBM_PEAK_GBS,
+            "model": "4*E*4 B per executed shot-iteration (every edge message read and written in "
+                     "both passes) + 398 B I/O per shot; the kernel keeps these bytes in LDS",
         },
         "cpu_baseline": cpu,
         "ler": ler,

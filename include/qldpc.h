@@ -135,10 +135,12 @@ typedef struct {
     int32_t early_stop;   /* 1: stop a shot once H e^(k) = s                 */
     int32_t prior_mode;   /* qldpc_prior_mode                                */
     int32_t layout;       /* qldpc_layout                                    */
+    int32_t waves_per_shot; /* block layout: wavefronts per shot, 8 or 16;
+                               0 = tuned choice                                */
 } qldpc_decode_params;
 
 /* Fills `p` with the defaults: F32, flooding, alpha 0.75, 32 iterations,
- * early stop on, per-shot priors, automatic layout. */
+ * early stop on, per-shot priors, automatic layout and waves per shot. */
 void qldpc_default_params(qldpc_decode_params *p);
 
 /* Decodes `batch` syndromes of one code.
@@ -157,6 +159,67 @@ qldpc_status qldpc_decode_batch(qldpc_code code, const qldpc_decode_params *para
                                 const uint32_t *syndromes, const void *priors, uint32_t *errors,
                                 uint8_t *converged, uint8_t *iters_used, float *posterior,
                                 void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Layout autotuner                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Times every kernel layout that can run `params` (wavefront per shot; one
+ * workgroup of 8 or 16 wavefronts per shot) on the caller's batch -- the
+ * buffers are those of qldpc_decode_batch, decoded several times -- and
+ * returns the fastest in `best` (layout and waves_per_shot filled in, other
+ * fields copied from `params`).  The choice is also recorded in the code
+ * object for this (format, schedule, prior mode, batch size class), and
+ * later calls with QLDPC_LAYOUT_AUTO use it.  Synchronises `stream`.
+ * Batch size classes: 1, 2-64, 65-1024, 1025-16384, > 16384 shots.  Without
+ * a recorded choice, AUTO uses the workgroup layout with 16 wavefronts for
+ * flooding below 512 shots and the wavefront layout otherwise. */
+qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, int32_t batch,
+                            const uint32_t *syndromes, const void *priors, uint32_t *errors,
+                            uint8_t *converged, uint8_t *iters_used, void *stream,
+                            qldpc_decode_params *best);
+
+/* Writes the recorded choices of `code` as one JSON object to `path`, or
+ * reads such a file back into `code` (entries for other lift sizes or code
+ * patterns are ignored). */
+qldpc_status qldpc_tune_save(qldpc_code code, const char *path);
+qldpc_status qldpc_tune_load(qldpc_code code, const char *path);
+
+/* ------------------------------------------------------------------------ */
+/* Latency sessions: host buffers in, host buffers out                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct qldpc_session_s *qldpc_session;
+
+typedef enum {
+    QLDPC_IO_COPY = 0,   /* pinned staging + copy-in, decode, copy-out on a
+                            private stream, captured once as a hipGraph per
+                            batch size                                          */
+    QLDPC_IO_MAPPED = 1  /* the kernel reads syndromes and writes results in
+                            pinned host memory directly (no copy commands)     */
+} qldpc_io_mode;
+
+/* A session owns device buffers and pinned host staging for up to
+ * `max_batch` shots, a private stream, and its captured graphs.  It measures
+ * what the paper's latency figure counts: host syndrome to host result. */
+qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *params,
+                                  int32_t max_batch, int32_t io_mode, qldpc_session *out);
+qldpc_status qldpc_session_destroy(qldpc_session s);
+
+/* Synchronous decode of `batch` <= max_batch shots from host buffers
+ * (syndromes uint32 [batch][ceil(m/32)], priors as in qldpc_decode_batch)
+ * into host buffers (errors, converged, iters_used may be NULL). */
+qldpc_status qldpc_session_decode(qldpc_session s, int32_t batch, const uint32_t *host_syndromes,
+                                  const void *host_priors, uint32_t *host_errors,
+                                  uint8_t *host_converged, uint8_t *host_iters);
+
+/* Runs `nreq` back-to-back session decodes of `batch` shots each, taking
+ * request i from shot (i * batch) mod pool of the host pools, and writes
+ * each request's end-to-end time in microseconds (steady clock) to
+ * lat_us[i]. */
+qldpc_status qldpc_session_latency(qldpc_session s, int32_t nreq, int32_t batch, int32_t pool,
+                                   const uint32_t *host_syndromes, const void *host_priors,
+                                   double *lat_us);
 
 /* Host helper: int8 Q4 prior clamp(round-half-away-from-zero(16 * llr),
  * -127, 127) for `count` values (host arrays). */

@@ -1,0 +1,259 @@
+// Workgroup-per-shot min-sum decoder (latency layout) for gfx950, flooding
+// schedule (Section 2, Algorithm 1).
+//
+// One workgroup of NW wavefronts decodes one shot of a lifted code with
+// L = 64 or 128.  A work item is one 64-row slice of a block row (check
+// pass) or of a block column (variable pass); item i is owned by wave
+// i mod NW, so every wave runs straight-line code for its own items with the
+// same constant LDS offsets as the wavefront layout.
+//
+// Per iteration k:
+//   A: check pass of iteration k; each block row also tests the decisions of
+//      iteration k-1 (s_R xor rot(e_C, a) over its blocks, 64-bit ballots in
+//      LDS) and raises a flag on a violated check;
+//   barrier; every wave reads the flag: all checks satisfied -> emit the
+//      outputs of iteration k-1 and stop (the check pass just run only
+//      overwrote messages, not e or Q);
+//   B: variable pass, a posteriori, decisions (ballots to LDS);
+//   barrier.
+// After the last iteration one more test pass decides the convergence flag.
+// Two barriers per iteration; flags are double buffered by iteration parity.
+#pragma once
+#include "decode_wave.h"
+
+namespace qldpc {
+
+template <class S, int L, int FMT, int NW>
+struct BlockLds {
+    using msg_t = typename Fmt<FMT>::msg_t;
+    static constexpr int PPL = L / 64;
+    static constexpr size_t msg_bytes = (size_t)S::SLOTS * L * sizeof(msg_t);
+    static constexpr size_t e_off = (msg_bytes + 15) & ~size_t(15);   // uint64 [NB][PPL]
+    static constexpr size_t f_off = e_off + (size_t)S::NB * PPL * 8;  // uint32 flags[2]
+    static constexpr size_t bytes = f_off + 16;
+};
+
+template <class S, int L, int FMT, int NW, bool PER_BIT, bool POST>
+__global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
+    using namespace wave;
+    static_assert(L == 64 || L == 128, "block layout needs L >= 64");
+    using Lay = BlockLds<S, L, FMT, NW>;
+    using msg_t = typename Fmt<FMT>::msg_t;
+    using prior_t = typename Fmt<FMT>::prior_t;
+    using acc_t = typename std::conditional<FMT == 0, float, int>::type;
+    constexpr int MB = S::MB, NB = S::NB, DC = S::DC, PPL = L / 64;
+    constexpr int N = NB * L;
+    constexpr int SW = (MB * L + 31) / 32, EW = (NB * L + 31) / 32;
+    constexpr int CN_ITEMS = MB * PPL, VN_ITEMS = NB * PPL;
+    constexpr int VN_PER_WAVE = (VN_ITEMS + NW - 1) / NW;
+
+    __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
+    msg_t *msg = reinterpret_cast<msg_t *>(lds);
+    uint64_t *emask = reinterpret_cast<uint64_t *>(lds + Lay::e_off);
+    uint32_t *flag = reinterpret_cast<uint32_t *>(lds + Lay::f_off);
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long shot = blockIdx.x;
+    const DevCode *__restrict__ code = a.code;
+
+    // syndrome bits of the checks this lane owns in each block row
+    uint32_t sb[PPL];
+#pragma unroll
+    for (int h = 0; h < PPL; ++h) {
+        sb[h] = 0;
+#pragma unroll
+        for (int R = 0; R < MB; ++R) {
+            const int m = R * L + lane + 64 * h;
+            sb[h] |= ((a.syn[shot * SW + (m >> 5)] >> (m & 31)) & 1u) << R;
+        }
+    }
+    // priors of this wave's variable items (canonicalised: no message is -0.0)
+    acc_t gam[PER_BIT ? VN_PER_WAVE : 1];
+    if constexpr (!PER_BIT) {
+        gam[0] = (acc_t) static_cast<const prior_t *>(a.prior)[shot];
+        if constexpr (FMT == 0) gam[0] = gam[0] + 0.0f;
+    } else {
+        static_for<0, VN_ITEMS>([&](auto Ic) {
+            constexpr int it = decltype(Ic)::value;
+            if (it % NW == wv) {
+                constexpr int C = it / PPL, h = it % PPL;
+                acc_t v = (acc_t) static_cast<const prior_t *>(a.prior)[shot * N + C * L + lane + 64 * h];
+                if constexpr (FMT == 0) v = v + 0.0f;
+                gam[it / NW] = v;
+            }
+        });
+    }
+    auto gamma_of = [&](int it) -> acc_t { return PER_BIT ? gam[it / NW] : gam[0]; };
+
+    // q^(0) = gamma on every edge: each wave initialises its variable items
+    static_for<0, VN_ITEMS>([&](auto Ic) {
+        constexpr int it = decltype(Ic)::value;
+        if (it % NW == wv) {
+            constexpr int C = it / PPL, h = it % PPL;
+            const acc_t gm = gamma_of(it);
+            static_for<0, S::T.col_deg[C]>([&](auto Jc) {
+                constexpr int i = decltype(Jc)::value;
+                constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
+                msg[slot * L + vn_index<L>(lane, h, (uint32_t)code->shift[slot])] = (msg_t)gm;
+            });
+        }
+    });
+    if (threadIdx.x == 0) {
+        flag[0] = 0;
+        flag[1] = 0;
+    }
+    acc_t Qr[POST ? VN_PER_WAVE : 1];
+    __syncthreads();
+
+    auto emit = [&](int k, bool conv) {
+        // e words straight from the ballots; conv / iters by thread 0
+        for (int w = threadIdx.x; w < EW; w += 64 * NW) {
+            const uint64_t m = emask[(w * 32) / 64];
+            a.err[shot * EW + w] = (uint32_t)(m >> ((w * 32) % 64));
+        }
+        if (threadIdx.x == 0) {
+            a.conv[shot] = conv ? 1 : 0;
+            if (a.iters) a.iters[shot] = (uint8_t)k;
+        }
+        if constexpr (POST) {
+            static_for<0, VN_ITEMS>([&](auto Ic) {
+                constexpr int it = decltype(Ic)::value;
+                if (it % NW == wv) {
+                    constexpr int C = it / PPL, h = it % PPL;
+                    acc_t Q = Qr[it / NW];
+                    float qv;
+                    if constexpr (FMT == 0) qv = Q;
+                    else qv = (float)Q * 0.0625f;
+                    a.post[shot * N + C * L + lane + 64 * h] = qv;
+                }
+            });
+        }
+    };
+
+    // syndrome test of the decisions in emask; raises flag[par] on a violation
+    auto test_rows = [&](int par) {
+        static_for<0, CN_ITEMS>([&](auto Ic) {
+            constexpr int it = decltype(Ic)::value;
+            if (it % NW == wv) {
+                constexpr int R = it / PPL, h = it % PPL;
+                uint64_t c = ballot(((sb[h] >> R) & 1u) != 0);
+                static_for<0, DC>([&](auto Jc) {
+                    constexpr int j = decltype(Jc)::value;
+                    constexpr int C = S::T.slot_bc[R][j];
+                    const uint32_t s = (uint32_t)code->shift[R * DC + j];
+                    if constexpr (L == 64) {
+                        const uint64_t e = emask[C];
+                        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)e);
+                        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(e >> 32));
+                        c ^= seg_rotr<64>(((uint64_t)hi << 32) | lo, s, 0);
+                    } else {
+                        const uint64_t e0 = emask[C * PPL], e1 = emask[C * PPL + 1];
+                        uint64_t lo, hi;
+                        rotr128(e0, e1, s, lo, hi);
+                        c ^= (h == 0) ? lo : hi;
+                    }
+                });
+                if (c != 0 && lane == 0) atomicOr(&flag[par], 1u);
+            }
+        });
+    };
+
+    int k = 1;
+    for (; k <= a.max_iters; ++k) {
+        // ---- A: check pass of iteration k, test of iteration k-1 ------------
+        static_for<0, CN_ITEMS>([&](auto Ic) {
+            constexpr int it = decltype(Ic)::value;
+            if (it % NW == wv) {
+                constexpr int R = it / PPL, h = it % PPL;
+                const uint32_t P = sb[h] << (31 - R);
+                if constexpr (FMT == 0) {
+                    float v[DC];
+#pragma unroll
+                    for (int j = 0; j < DC; ++j) v[j] = msg[(R * DC + j) * L + lane + 64 * h];
+                    cn_f32<DC>(v, P, a.alpha);
+#pragma unroll
+                    for (int j = 0; j < DC; ++j) msg[(R * DC + j) * L + lane + 64 * h] = v[j];
+                } else {
+                    int v[DC];
+#pragma unroll
+                    for (int j = 0; j < DC; ++j) v[j] = msg[(R * DC + j) * L + lane + 64 * h];
+                    cn_i8<DC>(v, P, a.alpha_num, a.alpha_shift);
+#pragma unroll
+                    for (int j = 0; j < DC; ++j) msg[(R * DC + j) * L + lane + 64 * h] = (msg_t)v[j];
+                }
+            }
+        });
+        if (k > 1 && a.early_stop) test_rows(k & 1);
+        __syncthreads();
+        if (k > 1 && a.early_stop && flag[k & 1] == 0) {
+            emit(k - 1, true);
+            return;
+        }
+        // ---- B: variable pass, a posteriori, decisions ----------------------
+        static_for<0, VN_ITEMS>([&](auto Ic) {
+            constexpr int it = decltype(Ic)::value;
+            if (it % NW == wv) {
+                constexpr int C = it / PPL, h = it % PPL;
+                constexpr int d = S::T.col_deg[C];
+                acc_t r[d];
+                int idx[d];
+                static_for<0, d>([&](auto Jc) {
+                    constexpr int i = decltype(Jc)::value;
+                    constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
+                    idx[i] = slot * L + vn_index<L>(lane, h, (uint32_t)code->shift[slot]);
+                    r[i] = (acc_t)msg[idx[i]];
+                });
+                acc_t Q;
+                if constexpr (FMT == 0) {
+                    float pre[d + 1];
+                    pre[0] = gamma_of(it);
+#pragma unroll
+                    for (int i = 0; i < d; ++i) pre[i + 1] = pre[i] + r[i];
+#pragma unroll
+                    for (int i = 0; i < d; ++i) {
+                        float q = pre[i];
+#pragma unroll
+                        for (int j = i + 1; j < d; ++j) q = q + r[j];
+                        msg[idx[i]] = q;
+                    }
+                    Q = pre[d];
+                } else {
+                    int sum = gamma_of(it);
+#pragma unroll
+                    for (int i = 0; i < d; ++i) sum += r[i];
+#pragma unroll
+                    for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
+                    Q = sum;
+                }
+                if constexpr (POST) Qr[it / NW] = Q;
+                const uint64_t m = ballot(Q < (acc_t)0);
+                if (lane == 0) emask[C * PPL + h] = m;
+            }
+        });
+        if (threadIdx.x == 0) flag[(k + 1) & 1] = 0;
+        __syncthreads();
+    }
+    // after the last iteration: one more test decides the flag
+    --k;
+    test_rows((k + 1) & 1);
+    __syncthreads();
+    emit(k, flag[(k + 1) & 1] == 0);
+}
+
+template <class S, int L, int FMT, int NW, bool PB, bool PO>
+hipError_t launch_block_one(const DecodeArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL((k_block<S, L, FMT, NW, PB, PO>), dim3((unsigned)a.batch), dim3(64 * NW), 0, st, a);
+    return hipGetLastError();
+}
+
+template <class S, int L, int FMT, int NW>
+hipError_t launch_block(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
+    if (k.per_bit)
+        return k.post ? launch_block_one<S, L, FMT, NW, true, true>(a, st)
+                      : launch_block_one<S, L, FMT, NW, true, false>(a, st);
+    return k.post ? launch_block_one<S, L, FMT, NW, false, true>(a, st)
+                  : launch_block_one<S, L, FMT, NW, false, false>(a, st);
+}
+
+}  // namespace qldpc

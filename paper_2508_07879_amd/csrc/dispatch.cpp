@@ -7,6 +7,8 @@ hipError_t launch_wave_L16(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wave_L32(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wave_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wave_L128(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_block_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_block_L128(const LaunchKey &, const DecodeArgs &, hipStream_t);
 
 hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t stream) {
     if (k.layout == 1) {
@@ -17,6 +19,10 @@ hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t st
             case 128: return launch_wave_L128(k, a, stream);
             default: break;
         }
+    }
+    if (k.layout == 2) {
+        if (k.L == 64) return launch_block_L64(k, a, stream);
+        if (k.L == 128) return launch_block_L128(k, a, stream);
     }
     return hipErrorNotSupported;
 }

@@ -38,6 +38,7 @@ struct LaunchKey {
     int per_bit;    // prior mode
     int post;       // posterior requested
     int layout;     // 1 = wave, 2 = block
+    int nw;         // block layout: wavefronts per shot
 };
 
 // Returns hipErrorNotSupported when no kernel exists for the key.
