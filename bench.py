@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--cpu-shots", type=int, default=8192, help="oracle sample per noise rate")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--latency-reqs", type=int, default=20000, help="requests per noise rate (0 = skip)")
     ap.add_argument("--seed", type=int, default=20250807)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run one plain device copy of MIB MiB (a known-size "
@@ -182,6 +183,33 @@ def main():
                 edge_model_GBps=float(sum(i * edge_model_bytes(E, bpm) + B * io_bytes for i in it_)
                                       / (k_.mean(axis=0).sum() * 1e-3) / 1e9))
 
+    # ---------------- latency: one syndrome per request, host to host ---------
+    latency = None
+    if args.latency_reqs > 0:
+        latency = {}
+        pool = 4096
+        for mode_name, early, iters in (("early_stop", 1, 32), ("all_32_iterations", 0, 32)):
+            prm = dec.params(fmt=abi.QLDPC_F32, sched=abi.QLDPC_FLOOD, max_iters=iters, early_stop=bool(early))
+            sess = abi.qldpc_session_create(dec.handle, prm, 1, abi.QLDPC_IO_MAPPED)
+            try:
+                per_p = {}
+                for bb in batches:
+                    syn_h = np.ascontiguousarray(bits.pack_bits(bb["batch"].s[:pool]))
+                    pr_h = np.ascontiguousarray(bb["batch"].gamma[:pool])
+                    abi.qldpc_session_latency(sess, 200, 1, pool, syn_h, pr_h)      # warm-up
+                    lat = abi.qldpc_session_latency(sess, args.latency_reqs, 1, pool, syn_h, pr_h)
+                    per_p[str(bb["p"])] = dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
+                                               p999=float(np.percentile(lat, 99.9)), mean=float(lat.mean()),
+                                               requests=int(lat.size))
+                    if mode_name == "all_32_iterations":
+                        break
+                latency[mode_name] = per_p
+            finally:
+                abi.qldpc_session_destroy(sess)
+        latency["definition"] = ("one syndrome per request, from host memory to the decision in host "
+                                 "memory (fine-grained pinned buffers read and written by the kernel), "
+                                 "workgroup-per-shot layout, FP32 flooding, steady-clock per request")
+
     # ---------------- CPU oracle on a bounded sample ---------------------------
     cpu = None
     if not args.no_cpu:
@@ -237,6 +265,7 @@ def main():
             "model": "4*E*4 B per executed shot-iteration (every edge message read and written in "
                      "both passes) + 398 B I/O per shot; the kernel keeps these bytes in LDS",
         },
+        "latency_us": latency,
         "cpu_baseline": cpu,
         "ler": ler,
         "variants": variants,

@@ -44,12 +44,13 @@ class Decoder:
         return (self.n + 31) // 32
 
     def params(self, fmt=abi.QLDPC_F32, sched=abi.QLDPC_FLOOD, alpha=0.75, max_iters=32,
-               early_stop=True, per_bit=False, layout=abi.QLDPC_LAYOUT_AUTO):
+               early_stop=True, per_bit=False, layout=abi.QLDPC_LAYOUT_AUTO, waves_per_shot=0):
         p = abi.qldpc_default_params()
         p.fmt, p.sched, p.alpha, p.max_iters = int(fmt), int(sched), float(alpha), int(max_iters)
         p.early_stop = int(bool(early_stop))
         p.prior_mode = abi.QLDPC_PRIOR_PER_BIT if per_bit else abi.QLDPC_PRIOR_PER_SHOT
         p.layout = int(layout)
+        p.waves_per_shot = int(waves_per_shot)
         return p
 
     def outputs(self, batch: int, posterior: bool = False):

@@ -27,6 +27,7 @@ QLDPC_F32, QLDPC_I8Q4 = 0, 1
 QLDPC_FLOOD, QLDPC_LAYERED = 0, 1
 QLDPC_PRIOR_PER_SHOT, QLDPC_PRIOR_PER_BIT = 0, 1
 QLDPC_LAYOUT_AUTO, QLDPC_LAYOUT_WAVE, QLDPC_LAYOUT_BLOCK = 0, 1, 2
+QLDPC_IO_COPY, QLDPC_IO_MAPPED = 0, 1
 
 
 class QldpcError(RuntimeError):
@@ -45,7 +46,7 @@ class qldpc_code_desc(C.Structure):
 class qldpc_decode_params(C.Structure):
     _fields_ = [("fmt", C.c_int32), ("sched", C.c_int32), ("alpha", C.c_float),
                 ("max_iters", C.c_int32), ("early_stop", C.c_int32),
-                ("prior_mode", C.c_int32), ("layout", C.c_int32)]
+                ("prior_mode", C.c_int32), ("layout", C.c_int32), ("waves_per_shot", C.c_int32)]
 
 
 def _load():
@@ -63,6 +64,14 @@ def _load():
         "qldpc_code_destroy": ([vp], i32),
         "qldpc_code_info": ([vp, vp, vp, vp, vp, vp], i32),
         "qldpc_decode_batch": ([vp, C.POINTER(qldpc_decode_params), i32, vp, vp, vp, vp, vp, vp, vp], i32),
+        "qldpc_autotune": ([vp, C.POINTER(qldpc_decode_params), i32, vp, vp, vp, vp, vp, vp,
+                            C.POINTER(qldpc_decode_params)], i32),
+        "qldpc_tune_save": ([vp, C.c_char_p], i32),
+        "qldpc_tune_load": ([vp, C.c_char_p], i32),
+        "qldpc_session_create": ([vp, C.POINTER(qldpc_decode_params), i32, i32, C.POINTER(vp)], i32),
+        "qldpc_session_destroy": ([vp], i32),
+        "qldpc_session_decode": ([vp, i32, vp, vp, vp, vp, vp], i32),
+        "qldpc_session_latency": ([vp, i32, i32, i32, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -144,3 +153,49 @@ def qldpc_decode_batch(h, params: qldpc_decode_params, batch: int, syndromes, pr
     _check(lib.qldpc_decode_batch(h, C.byref(params), int(batch), _ptr(syndromes), _ptr(priors),
                                   _ptr(errors), _ptr(converged), _ptr(iters_used), _ptr(posterior),
                                   _stream(stream)))
+
+
+def qldpc_autotune(h, params: qldpc_decode_params, batch: int, syndromes, priors, errors, converged,
+                   iters_used=None, stream=None) -> qldpc_decode_params:
+    best = qldpc_decode_params()
+    _check(lib.qldpc_autotune(h, C.byref(params), int(batch), _ptr(syndromes), _ptr(priors), _ptr(errors),
+                              _ptr(converged), _ptr(iters_used), _stream(stream), C.byref(best)))
+    return best
+
+
+def qldpc_tune_save(h, path: str) -> None:
+    _check(lib.qldpc_tune_save(h, path.encode()))
+
+
+def qldpc_tune_load(h, path: str) -> None:
+    _check(lib.qldpc_tune_load(h, path.encode()))
+
+
+def _np(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def qldpc_session_create(h, params: qldpc_decode_params, max_batch: int, io_mode: int = QLDPC_IO_COPY):
+    s = C.c_void_p()
+    _check(lib.qldpc_session_create(h, C.byref(params), int(max_batch), int(io_mode), C.byref(s)))
+    return s
+
+
+def qldpc_session_destroy(s) -> None:
+    _check(lib.qldpc_session_destroy(s))
+
+
+def qldpc_session_decode(s, batch: int, host_syndromes: np.ndarray, host_priors: np.ndarray,
+                         host_errors: np.ndarray, host_converged: np.ndarray = None,
+                         host_iters: np.ndarray = None) -> None:
+    """Host numpy arrays in and out (C-contiguous)."""
+    _check(lib.qldpc_session_decode(s, int(batch), _np(host_syndromes), _np(host_priors), _np(host_errors),
+                                    _np(host_converged), _np(host_iters)))
+
+
+def qldpc_session_latency(s, nreq: int, batch: int, pool: int, host_syndromes: np.ndarray,
+                          host_priors: np.ndarray) -> np.ndarray:
+    lat = np.zeros(int(nreq), np.float64)
+    _check(lib.qldpc_session_latency(s, int(nreq), int(batch), int(pool), _np(host_syndromes),
+                                     _np(host_priors), _np(lat)))
+    return lat

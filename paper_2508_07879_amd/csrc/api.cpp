@@ -11,33 +11,102 @@
 #include <string>
 #include <vector>
 
-#include "../../include/qldpc.h"
-#include "kernels.h"
+#include <fstream>
+#include <sstream>
+
+#include "internal.h"
 #include "shapes.h"
 
 using namespace qldpc;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-qldpc_status fail(qldpc_status st, const std::string &msg) {
+namespace qldpc {
+
+qldpc_status set_error(qldpc_status st, const std::string &msg) {
     g_err = msg;
     return st;
 }
 
-qldpc_status hip_fail(hipError_t e, const char *what) {
-    return fail(QLDPC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+qldpc_status hip_error(hipError_t e, const char *what) {
+    return set_error(QLDPC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+}  // namespace qldpc
+
+namespace {
+qldpc_status fail(qldpc_status st, const std::string &msg) { return set_error(st, msg); }
+qldpc_status hip_fail(hipError_t e, const char *what) { return hip_error(e, what); }
 }  // namespace
 
-struct qldpc_code_s {
-    int32_t m = 0, n = 0, nnz = 0, max_dc = 0, max_dv = 0;
-    int32_t L = 0, which = -1, device = 0;
-    std::vector<int32_t> shift;    // per slot (R * 8 + j)
-    DevCode *dev = nullptr;        // device copy of the shift tables
-};
+namespace qldpc {
+
+qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32_t batch, LaunchKey *key,
+                            DecodeArgs *a) {
+    if (!code || !p) return fail(QLDPC_ERR_INVALID_ARG, "decode: null code or params");
+    if (batch < 0) return fail(QLDPC_ERR_INVALID_ARG, "decode: negative batch");
+    if (p->max_iters < 1 || p->max_iters > 255)
+        return fail(QLDPC_ERR_INVALID_ARG, "decode: max_iters must be in [1, 255]");
+    if (p->fmt != QLDPC_F32 && p->fmt != QLDPC_I8Q4) return fail(QLDPC_ERR_INVALID_ARG, "decode: bad format");
+    if (p->sched != QLDPC_FLOOD && p->sched != QLDPC_LAYERED)
+        return fail(QLDPC_ERR_INVALID_ARG, "decode: bad schedule");
+    if (p->prior_mode != QLDPC_PRIOR_PER_SHOT && p->prior_mode != QLDPC_PRIOR_PER_BIT)
+        return fail(QLDPC_ERR_INVALID_ARG, "decode: bad prior mode");
+    if (!(p->alpha > 0.0f && p->alpha <= 1.0f)) return fail(QLDPC_ERR_INVALID_ARG, "decode: alpha must be in (0, 1]");
+    if (p->layout < QLDPC_LAYOUT_AUTO || p->layout > QLDPC_LAYOUT_BLOCK)
+        return fail(QLDPC_ERR_INVALID_ARG, "decode: bad layout");
+    if (p->waves_per_shot != 0 && p->waves_per_shot != 8 && p->waves_per_shot != 16)
+        return fail(QLDPC_ERR_INVALID_ARG, "decode: waves_per_shot must be 0, 8 or 16");
+    *a = DecodeArgs{};
+    a->code = code->dev;
+    a->batch = batch;
+    a->max_iters = p->max_iters;
+    a->early_stop = p->early_stop ? 1 : 0;
+    a->alpha = p->alpha;
+    if (p->fmt == QLDPC_I8Q4) {
+        int sh = 0;
+        for (; sh <= 8; ++sh) {
+            const float num = p->alpha * (float)(1 << sh);
+            if (num == std::floor(num)) break;
+        }
+        if (sh > 8) return fail(QLDPC_ERR_UNSUPPORTED, "decode: int8 needs alpha = num / 2^s, s <= 8");
+        a->alpha_num = (int32_t)(p->alpha * (float)(1 << sh));
+        a->alpha_shift = sh;
+    }
+    *key = LaunchKey{};
+    key->which = code->which;
+    key->L = code->L;
+    key->fmt = p->fmt;
+    key->sched = p->sched;
+    key->per_bit = p->prior_mode == QLDPC_PRIOR_PER_BIT;
+    const bool block_ok = p->sched == QLDPC_FLOOD && code->L >= 64;
+    int layout = p->layout, nw = p->waves_per_shot;
+    if (layout == QLDPC_LAYOUT_AUTO) {
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> g(code->tune_mu);
+            auto it = code->tune.find(tune_key(p->fmt, p->sched, p->prior_mode, size_class(batch)));
+            if (it != code->tune.end()) {
+                layout = it->second.layout;
+                if (nw == 0) nw = it->second.nw;
+                found = true;
+            }
+        }
+        if (!found) layout = (block_ok && batch < 512) ? QLDPC_LAYOUT_BLOCK : QLDPC_LAYOUT_WAVE;
+    }
+    if (layout == QLDPC_LAYOUT_BLOCK) {
+        if (!block_ok)
+            return fail(QLDPC_ERR_UNSUPPORTED, "decode: the workgroup layout needs flooding and L >= 64");
+        if (nw == 0) nw = 16;
+    }
+    key->layout = layout;
+    key->nw = nw;
+    return QLDPC_OK;
+}
+
+}  // namespace qldpc
 
 extern "C" {
 
@@ -54,6 +123,7 @@ void qldpc_default_params(qldpc_decode_params *p) {
     p->early_stop = 1;
     p->prior_mode = QLDPC_PRIOR_PER_SHOT;
     p->layout = QLDPC_LAYOUT_AUTO;
+    p->waves_per_shot = 0;
 }
 
 qldpc_status qldpc_quantize_prior(const float *llr, int8_t *out, int64_t count) {
@@ -157,7 +227,6 @@ qldpc_status qldpc_code_create(const qldpc_code_desc *d, int32_t device, qldpc_c
             }
             host.lowmask[R * 8 + j] = low;
         }
-    code->shift.assign(host.shift, host.shift + kMaxSlots);
     int prev = 0;
     hipError_t e = hipGetDevice(&prev);
     if (e != hipSuccess) { delete code; return hip_fail(e, "hipGetDevice"); }
@@ -201,52 +270,128 @@ qldpc_status qldpc_code_info(qldpc_code c, int32_t *m, int32_t *n, int32_t *nnz,
 qldpc_status qldpc_decode_batch(qldpc_code code, const qldpc_decode_params *p, int32_t batch,
                                 const uint32_t *syn, const void *priors, uint32_t *err,
                                 uint8_t *conv, uint8_t *iters, float *post, void *stream) {
-    if (!code || !p) return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: null code or params");
-    if (batch < 0) return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: negative batch");
-    if (p->max_iters < 1 || p->max_iters > 255)
-        return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: max_iters must be in [1, 255]");
-    if (p->fmt != QLDPC_F32 && p->fmt != QLDPC_I8Q4) return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: bad format");
-    if (p->sched != QLDPC_FLOOD && p->sched != QLDPC_LAYERED)
-        return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: bad schedule");
-    if (p->prior_mode != QLDPC_PRIOR_PER_SHOT && p->prior_mode != QLDPC_PRIOR_PER_BIT)
-        return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: bad prior mode");
-    if (!(p->alpha > 0.0f && p->alpha <= 1.0f)) return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: alpha must be in (0, 1]");
-    if (batch == 0) return QLDPC_OK;
-    if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: null buffer");
+    LaunchKey k{};
     DecodeArgs a{};
-    a.code = code->dev;
+    qldpc_status st = prepare_decode(code, p, batch, &k, &a);
+    if (st != QLDPC_OK || batch == 0) return st;
+    if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: null buffer");
     a.syn = syn;
     a.prior = priors;
     a.err = err;
     a.conv = conv;
     a.iters = iters;
     a.post = post;
-    a.batch = batch;
-    a.max_iters = p->max_iters;
-    a.early_stop = p->early_stop ? 1 : 0;
-    a.alpha = p->alpha;
-    if (p->fmt == QLDPC_I8Q4) {
-        int sh = 0;
-        for (; sh <= 8; ++sh) {
-            const float num = p->alpha * (float)(1 << sh);
-            if (num == std::floor(num)) break;
-        }
-        if (sh > 8) return fail(QLDPC_ERR_UNSUPPORTED, "decode_batch: int8 needs alpha = num / 2^s, s <= 8");
-        a.alpha_num = (int32_t)(p->alpha * (float)(1 << sh));
-        a.alpha_shift = sh;
-    }
-    LaunchKey k{};
-    k.which = code->which;
-    k.L = code->L;
-    k.fmt = p->fmt;
-    k.sched = p->sched;
-    k.per_bit = p->prior_mode == QLDPC_PRIOR_PER_BIT;
     k.post = post != nullptr;
-    k.layout = p->layout == QLDPC_LAYOUT_AUTO ? QLDPC_LAYOUT_WAVE : p->layout;
     const hipError_t e = launch_decode(k, a, (hipStream_t)stream);
     if (e == hipErrorNotSupported)
         return fail(QLDPC_ERR_UNSUPPORTED, "decode_batch: no kernel for this format/schedule/layout/L");
     if (e != hipSuccess) return hip_fail(e, "decode_batch launch");
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, int32_t batch,
+                            const uint32_t *syn, const void *priors, uint32_t *err, uint8_t *conv,
+                            uint8_t *iters, void *stream, qldpc_decode_params *best) {
+    if (!code || !params || !best) return fail(QLDPC_ERR_INVALID_ARG, "autotune: null argument");
+    if (batch <= 0) return fail(QLDPC_ERR_INVALID_ARG, "autotune: batch must be positive");
+    if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, "autotune: null buffer");
+    struct Cand { int layout, nw; };
+    std::vector<Cand> cands = {{QLDPC_LAYOUT_WAVE, 0}};
+    if (params->sched == QLDPC_FLOOD && code->L >= 64) {
+        cands.push_back({QLDPC_LAYOUT_BLOCK, 8});
+        cands.push_back({QLDPC_LAYOUT_BLOCK, 16});
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    hipError_t he = hipEventCreate(&e0);
+    if (he != hipSuccess) return hip_fail(he, "autotune: event");
+    he = hipEventCreate(&e1);
+    if (he != hipSuccess) { hipEventDestroy(e0); return hip_fail(he, "autotune: event"); }
+    TuneChoice bestc{};
+    bestc.ms = 1e30f;
+    qldpc_status rc = QLDPC_OK;
+    for (const Cand &c : cands) {
+        qldpc_decode_params q = *params;
+        q.layout = c.layout;
+        q.waves_per_shot = c.nw;
+        rc = qldpc_decode_batch(code, &q, batch, syn, priors, err, conv, iters, nullptr, stream);  // warm-up
+        if (rc != QLDPC_OK) break;
+        const int reps = 3;
+        hipEventRecord(e0, st);
+        for (int r = 0; r < reps && rc == QLDPC_OK; ++r)
+            rc = qldpc_decode_batch(code, &q, batch, syn, priors, err, conv, iters, nullptr, stream);
+        hipEventRecord(e1, st);
+        if (rc != QLDPC_OK) break;
+        he = hipEventSynchronize(e1);
+        if (he != hipSuccess) { rc = hip_fail(he, "autotune: synchronize"); break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < bestc.ms) bestc = TuneChoice{c.layout, c.nw, ms};
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != QLDPC_OK) return rc;
+    {
+        std::lock_guard<std::mutex> g(code->tune_mu);
+        code->tune[tune_key(params->fmt, params->sched, params->prior_mode, size_class(batch))] = bestc;
+    }
+    *best = *params;
+    best->layout = bestc.layout;
+    best->waves_per_shot = bestc.nw;
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_tune_save(qldpc_code code, const char *path) {
+    if (!code || !path) return fail(QLDPC_ERR_INVALID_ARG, "tune_save: null argument");
+    std::ostringstream o;
+    o << "{\"L\": " << code->L << ", \"pattern\": " << code->which << ", \"entries\": [";
+    {
+        std::lock_guard<std::mutex> g(code->tune_mu);
+        bool first = true;
+        for (const auto &kv : code->tune) {
+            o << (first ? "" : ", ") << "[" << kv.first << ", " << kv.second.layout << ", "
+              << kv.second.nw << ", " << kv.second.ms << "]";
+            first = false;
+        }
+    }
+    o << "]}\n";
+    std::ofstream f(path);
+    if (!f) return fail(QLDPC_ERR_INVALID_ARG, std::string("tune_save: cannot write ") + path);
+    f << o.str();
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_tune_load(qldpc_code code, const char *path) {
+    if (!code || !path) return fail(QLDPC_ERR_INVALID_ARG, "tune_load: null argument");
+    std::ifstream f(path);
+    if (!f) return fail(QLDPC_ERR_INVALID_ARG, std::string("tune_load: cannot read ") + path);
+    std::stringstream buf;
+    buf << f.rdbuf();
+    std::string t = buf.str();
+    for (char &ch : t)
+        if (ch == '[' || ch == ']' || ch == '{' || ch == '}' || ch == ',' || ch == ':' || ch == '"') ch = ' ';
+    std::istringstream in(t);
+    std::string tok;
+    int L = -1, pattern = -1;
+    std::vector<double> nums;
+    while (in >> tok) {
+        if (tok == "L") in >> L;
+        else if (tok == "pattern") in >> pattern;
+        else if (tok == "entries") {
+            double v;
+            while (in >> v) nums.push_back(v);
+        }
+    }
+    if (L < 0 || pattern < 0 || nums.size() % 4 != 0) return fail(QLDPC_ERR_INVALID_ARG, "tune_load: malformed file");
+    if (L != code->L || pattern != code->which) return QLDPC_OK;   // for another code
+    std::lock_guard<std::mutex> g(code->tune_mu);
+    for (size_t i = 0; i < nums.size(); i += 4) {
+        const int layout = (int)nums[i + 1], nw = (int)nums[i + 2];
+        if (layout != QLDPC_LAYOUT_WAVE && layout != QLDPC_LAYOUT_BLOCK) continue;
+        if (layout == QLDPC_LAYOUT_BLOCK && nw != 8 && nw != 16) continue;
+        code->tune[(int)nums[i]] = TuneChoice{layout, nw, (float)nums[i + 3]};
+    }
     return QLDPC_OK;
 }
 

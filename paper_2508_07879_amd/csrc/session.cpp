@@ -1,0 +1,247 @@
+// Latency sessions: host syndromes in, host decisions out, timed end to end
+// as the paper's latency figure counts it (host-to-device copy, decode,
+// device-to-host copy; Section 3).
+//
+// QLDPC_IO_COPY: inputs are copied into pinned staging, then a hipGraph
+// captured once per batch size replays copy-in -> decode -> copy-out on the
+// session's stream.  QLDPC_IO_MAPPED: the decoder reads the pinned staging
+// and writes its results there directly (the GPU reaches host memory over
+// the bus), so a request is one kernel launch.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "internal.h"
+
+using namespace qldpc;
+
+struct qldpc_session_s {
+    qldpc_code code = nullptr;
+    qldpc_decode_params params{};
+    int32_t max_batch = 0;
+    int32_t io_mode = 0;
+    int32_t syn_words = 0, err_words = 0;
+    size_t prior_bytes_per_shot = 0;
+    hipStream_t stream = nullptr;
+    // device buffers (COPY mode)
+    uint32_t *d_syn = nullptr;
+    void *d_prior = nullptr;
+    uint32_t *d_err = nullptr;
+    uint8_t *d_conv = nullptr, *d_iters = nullptr;
+    // pinned host staging
+    uint32_t *h_syn = nullptr;
+    void *h_prior = nullptr;
+    uint32_t *h_err = nullptr;
+    uint8_t *h_conv = nullptr, *h_iters = nullptr;
+    // device-side addresses of the staging buffers (MAPPED mode)
+    uint32_t *m_syn = nullptr;
+    void *m_prior = nullptr;
+    uint32_t *m_err = nullptr;
+    uint8_t *m_conv = nullptr, *m_iters = nullptr;
+    std::map<int32_t, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+void release(qldpc_session s) {
+    for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+    if (s->d_syn) hipFree(s->d_syn);
+    if (s->d_prior) hipFree(s->d_prior);
+    if (s->d_err) hipFree(s->d_err);
+    if (s->d_conv) hipFree(s->d_conv);
+    if (s->d_iters) hipFree(s->d_iters);
+    if (s->h_syn) hipHostFree(s->h_syn);
+    if (s->h_prior) hipHostFree(s->h_prior);
+    if (s->h_err) hipHostFree(s->h_err);
+    if (s->h_conv) hipHostFree(s->h_conv);
+    if (s->h_iters) hipHostFree(s->h_iters);
+    if (s->stream) hipStreamDestroy(s->stream);
+    delete s;
+}
+
+// Enqueues one decode of `batch` shots from the staging buffers.
+qldpc_status enqueue(qldpc_session s, int32_t batch) {
+    LaunchKey k{};
+    DecodeArgs a{};
+    qldpc_status st = prepare_decode(s->code, &s->params, batch, &k, &a);
+    if (st != QLDPC_OK) return st;
+    if (s->io_mode == QLDPC_IO_MAPPED) {
+        a.syn = s->m_syn;
+        a.prior = s->m_prior;
+        a.err = s->m_err;
+        a.conv = s->m_conv;
+        a.iters = s->m_iters;
+    } else {
+        a.syn = s->d_syn;
+        a.prior = s->d_prior;
+        a.err = s->d_err;
+        a.conv = s->d_conv;
+        a.iters = s->d_iters;
+    }
+    a.post = nullptr;
+    k.post = 0;
+    hipError_t e = launch_decode(k, a, s->stream);
+    if (e == hipErrorNotSupported) return set_error(QLDPC_ERR_UNSUPPORTED, "session: no kernel for these parameters");
+    if (e != hipSuccess) return hip_error(e, "session: launch");
+    return QLDPC_OK;
+}
+
+qldpc_status graph_for(qldpc_session s, int32_t batch, hipGraphExec_t *out) {
+    auto it = s->graphs.find(batch);
+    if (it != s->graphs.end()) {
+        *out = it->second;
+        return QLDPC_OK;
+    }
+    hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error(e, "session: begin capture");
+    qldpc_status st = QLDPC_OK;
+    const size_t sb = (size_t)batch * s->syn_words * 4, pb = (size_t)batch * s->prior_bytes_per_shot;
+    const size_t eb = (size_t)batch * s->err_words * 4;
+    hipMemcpyAsync(s->d_syn, s->h_syn, sb, hipMemcpyHostToDevice, s->stream);
+    hipMemcpyAsync(s->d_prior, s->h_prior, pb, hipMemcpyHostToDevice, s->stream);
+    st = enqueue(s, batch);
+    hipMemcpyAsync(s->h_err, s->d_err, eb, hipMemcpyDeviceToHost, s->stream);
+    hipMemcpyAsync(s->h_conv, s->d_conv, (size_t)batch, hipMemcpyDeviceToHost, s->stream);
+    hipMemcpyAsync(s->h_iters, s->d_iters, (size_t)batch, hipMemcpyDeviceToHost, s->stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s->stream, &g);
+    if (st != QLDPC_OK) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_error(e, "session: end capture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_error(e, "session: instantiate");
+    s->graphs[batch] = ex;
+    *out = ex;
+    return QLDPC_OK;
+}
+
+// Decode from the staging buffers, synchronously.
+qldpc_status run_staged(qldpc_session s, int32_t batch) {
+    hipError_t e;
+    if (s->io_mode == QLDPC_IO_MAPPED) {
+        qldpc_status st = enqueue(s, batch);
+        if (st != QLDPC_OK) return st;
+    } else {
+        hipGraphExec_t g = nullptr;
+        qldpc_status st = graph_for(s, batch, &g);
+        if (st != QLDPC_OK) return st;
+        e = hipGraphLaunch(g, s->stream);
+        if (e != hipSuccess) return hip_error(e, "session: graph launch");
+    }
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_error(e, "session: synchronize");
+    return QLDPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *params, int32_t max_batch,
+                                  int32_t io_mode, qldpc_session *out) {
+    if (!code || !params || !out) return set_error(QLDPC_ERR_INVALID_ARG, "session_create: null argument");
+    if (max_batch <= 0) return set_error(QLDPC_ERR_INVALID_ARG, "session_create: max_batch must be positive");
+    if (io_mode != QLDPC_IO_COPY && io_mode != QLDPC_IO_MAPPED)
+        return set_error(QLDPC_ERR_INVALID_ARG, "session_create: bad io mode");
+    LaunchKey k{};
+    DecodeArgs a{};
+    qldpc_status st = prepare_decode(code, params, max_batch, &k, &a);   // validates params
+    if (st != QLDPC_OK) return st;
+    auto *s = new (std::nothrow) qldpc_session_s();
+    if (!s) return set_error(QLDPC_ERR_OUT_OF_MEMORY, "session_create: host allocation");
+    s->code = code;
+    s->params = *params;
+    s->max_batch = max_batch;
+    s->io_mode = io_mode;
+    s->syn_words = (code->m + 31) / 32;
+    s->err_words = (code->n + 31) / 32;
+    const size_t vbytes = params->fmt == QLDPC_F32 ? 4 : 1;
+    s->prior_bytes_per_shot = params->prior_mode == QLDPC_PRIOR_PER_BIT ? vbytes * code->n : vbytes;
+    const size_t B = (size_t)max_batch;
+    // MAPPED: fine-grained (coherent) pinned memory the kernel reads and writes
+    // over the bus; COPY: ordinary pinned staging for the copy engines.
+    const unsigned fl = io_mode == QLDPC_IO_MAPPED ? (hipHostMallocMapped | hipHostMallocCoherent)
+                                                   : hipHostMallocDefault;
+    hipError_t e = hipSetDevice(code->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_syn, B * s->syn_words * 4, fl);
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_prior, B * s->prior_bytes_per_shot, fl);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_err, B * s->err_words * 4, fl);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_conv, B, fl);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_iters, B, fl);
+    if (e == hipSuccess && io_mode == QLDPC_IO_MAPPED) {
+        e = hipHostGetDevicePointer((void **)&s->m_syn, s->h_syn, 0);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(&s->m_prior, s->h_prior, 0);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->m_err, s->h_err, 0);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->m_conv, s->h_conv, 0);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->m_iters, s->h_iters, 0);
+    }
+    if (e == hipSuccess && io_mode == QLDPC_IO_COPY) {
+        e = hipMalloc((void **)&s->d_syn, B * s->syn_words * 4);
+        if (e == hipSuccess) e = hipMalloc(&s->d_prior, B * s->prior_bytes_per_shot);
+        if (e == hipSuccess) e = hipMalloc((void **)&s->d_err, B * s->err_words * 4);
+        if (e == hipSuccess) e = hipMalloc((void **)&s->d_conv, B);
+        if (e == hipSuccess) e = hipMalloc((void **)&s->d_iters, B);
+    }
+    if (e != hipSuccess) {
+        release(s);
+        return set_error(QLDPC_ERR_OUT_OF_MEMORY, std::string("session_create: ") + hipGetErrorString(e));
+    }
+    *out = s;
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_session_destroy(qldpc_session s) {
+    if (!s) return QLDPC_OK;
+    if (s->stream) hipStreamSynchronize(s->stream);
+    release(s);
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_session_decode(qldpc_session s, int32_t batch, const uint32_t *host_syn,
+                                  const void *host_prior, uint32_t *host_err, uint8_t *host_conv,
+                                  uint8_t *host_iters) {
+    if (!s) return set_error(QLDPC_ERR_INVALID_ARG, "session_decode: null session");
+    if (batch < 0 || batch > s->max_batch) return set_error(QLDPC_ERR_INVALID_ARG, "session_decode: batch out of range");
+    if (batch == 0) return QLDPC_OK;
+    if (!host_syn || !host_prior) return set_error(QLDPC_ERR_INVALID_ARG, "session_decode: null input");
+    std::memcpy(s->h_syn, host_syn, (size_t)batch * s->syn_words * 4);
+    std::memcpy(s->h_prior, host_prior, (size_t)batch * s->prior_bytes_per_shot);
+    qldpc_status st = run_staged(s, batch);
+    if (st != QLDPC_OK) return st;
+    if (host_err) std::memcpy(host_err, s->h_err, (size_t)batch * s->err_words * 4);
+    if (host_conv) std::memcpy(host_conv, s->h_conv, (size_t)batch);
+    if (host_iters) std::memcpy(host_iters, s->h_iters, (size_t)batch);
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_session_latency(qldpc_session s, int32_t nreq, int32_t batch, int32_t pool,
+                                   const uint32_t *host_syn, const void *host_prior, double *lat_us) {
+    if (!s || !host_syn || !host_prior || !lat_us) return set_error(QLDPC_ERR_INVALID_ARG, "session_latency: null argument");
+    if (nreq < 0 || batch <= 0 || batch > s->max_batch || pool < batch)
+        return set_error(QLDPC_ERR_INVALID_ARG, "session_latency: bad sizes");
+    std::vector<uint32_t> err((size_t)batch * s->err_words);
+    std::vector<uint8_t> conv(batch), it(batch);
+    const char *pr = static_cast<const char *>(host_prior);
+    for (int32_t i = 0; i < nreq; ++i) {
+        int64_t start = ((int64_t)i * batch) % pool;
+        if (start + batch > pool) start = 0;
+        const auto t0 = std::chrono::steady_clock::now();
+        qldpc_status st = qldpc_session_decode(s, batch, host_syn + start * s->syn_words,
+                                               pr + start * s->prior_bytes_per_shot, err.data(), conv.data(),
+                                               it.data());
+        const auto t1 = std::chrono::steady_clock::now();
+        if (st != QLDPC_OK) return st;
+        lat_us[i] = std::chrono::duration<double, std::micro>(t1 - t0).count();
+    }
+    return QLDPC_OK;
+}
+
+}  // extern "C"

@@ -17,7 +17,7 @@ def to_dev(x, dtype=None):
 
 
 def gpu_decode(dec, s_bits, prior, fmt=0, sched=0, alpha=0.75, max_iters=32, early_stop=True,
-               per_bit=False, posterior=True, layout=0):
+               per_bit=False, posterior=True, layout=0, waves_per_shot=0):
     """Decode uint8 syndrome bits [B, m] on the device; returns host arrays."""
     import torch
     syn = to_dev(bits.pack_bits(s_bits).view(np.int32))
@@ -26,7 +26,7 @@ def gpu_decode(dec, s_bits, prior, fmt=0, sched=0, alpha=0.75, max_iters=32, ear
     else:
         pr = to_dev(np.asarray(prior, np.int8))
     p = dec.params(fmt=fmt, sched=sched, alpha=alpha, max_iters=max_iters, early_stop=early_stop,
-                   per_bit=per_bit, layout=layout)
+                   per_bit=per_bit, layout=layout, waves_per_shot=waves_per_shot)
     err, conv, it, post = dec.decode(syn, pr, p, posterior=posterior)
     torch.cuda.synchronize()
     e = bits.unpack_bits(err.cpu().numpy().view(np.uint32), dec.n)

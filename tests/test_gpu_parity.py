@@ -53,7 +53,7 @@ def run_case(L, shots, p, fmt=0, sched=0, per_bit=False, seed=7, max_iters=32, e
         prior = q
         scale = None
     g = gpu_decode(dec, s, prior, fmt=fmt, sched=sched, max_iters=max_iters, early_stop=early_stop,
-                   per_bit=per_bit, alpha=alpha)
+                   per_bit=per_bit, alpha=alpha, layout=abi.QLDPC_LAYOUT_WAVE)
     o = oracle_decode(H, s, prior, fmt=fmt, sched=sched, max_iters=max_iters, early_stop=early_stop,
                       layer_size=L, alpha=alpha)
     assert_parity(g, o, scale, fmt, tag=f"L={L} p={p} fmt={fmt} sched={sched} pb={per_bit}")
@@ -125,10 +125,11 @@ def test_single_shot_and_empty_batch():
 def test_deterministic_and_order_independent():
     c, H, dec = code(64)
     b = noise.Batch(c.hz, 26, np.arange(128), 0.05)
-    g1 = gpu_decode(dec, b.s, b.gamma)
-    g2 = gpu_decode(dec, b.s, b.gamma)
+    W = abi.QLDPC_LAYOUT_WAVE
+    g1 = gpu_decode(dec, b.s, b.gamma, layout=W)
+    g2 = gpu_decode(dec, b.s, b.gamma, layout=W)
     perm = np.random.default_rng(0).permutation(128)
-    g3 = gpu_decode(dec, b.s[perm], b.gamma[perm])
+    g3 = gpu_decode(dec, b.s[perm], b.gamma[perm], layout=W)
     for a_, b_ in zip(g1, g2):
         assert np.array_equal(a_, b_)
     for a_, b_ in zip(g1, g3):
@@ -159,7 +160,7 @@ def test_full_batch_sampled(fmt, sched):
     B = 65536
     b = noise.Batch(c.hz, 1000 + fmt + 2 * sched, np.arange(B), 0.05)
     prior = b.gamma if fmt == 0 else b.gamma_q4()
-    g = gpu_decode(dec, b.s, prior, fmt=fmt, sched=sched, posterior=False)
+    g = gpu_decode(dec, b.s, prior, fmt=fmt, sched=sched, posterior=False, layout=abi.QLDPC_LAYOUT_WAVE)
     e, conv, it, _ = g
     ok = conv == 1
     assert np.array_equal(noise.syndromes(c.hz, e[ok]), b.s[ok])
