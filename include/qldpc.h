@@ -221,6 +221,48 @@ qldpc_status qldpc_session_latency(qldpc_session s, int32_t nreq, int32_t batch,
                                    const uint32_t *host_syndromes, const void *host_priors,
                                    double *lat_us);
 
+/* ------------------------------------------------------------------------ */
+/* Neural min-sum: flooding min-sum whose check rule scales edge e at        */
+/* iteration k by a learned weight w[k][e] instead of alpha (Section 2,      */
+/* Algorithm 1, check-node update, with alpha generalised per edge and       */
+/* iteration).  FP32 messages, per-shot priors, lifted codes with            */
+/* L in {32, 64, 128} (H_Z pattern).  Weights are device float [T][nnz],     */
+/* edge e = CSR position, 16-byte aligned.  Training runs exactly T          */
+/* iterations without early stop.                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Device workspace the forward pass fills and the backward pass reads:
+ * every iteration's check-node inputs plus per-wavefront gradient slices
+ * (about T * batch * nnz * 4 bytes). */
+qldpc_status qldpc_nbp_workspace_bytes(qldpc_code code, int32_t batch, int32_t T, size_t *bytes);
+
+/* posteriors: device float [T][batch][n], out: Q^(k) of iterations 1..T.
+ * syndromes and priors as in qldpc_decode_batch (priors [batch]).
+ * workspace: device, qldpc_nbp_workspace_bytes, caller-owned. */
+qldpc_status qldpc_nbp_forward(qldpc_code code, int32_t batch, int32_t T, const float *weights,
+                               const uint32_t *syndromes, const float *priors, float *posteriors,
+                               void *workspace, void *stream);
+
+/* Reverse-mode derivative of the forward map.  grad_posteriors: device
+ * float [T][batch][n] = dL/dQ^(k); grad_weights: device float [T][nnz], out
+ * (overwritten) = dL/dw summed over the batch.  workspace must hold the
+ * forward pass of the same inputs and weights.  Signs carry no gradient;
+ * the minimum routes its gradient to the lowest-index edge on ties.  The
+ * result is bit-reproducible (fixed-order reduction, no atomics). */
+qldpc_status qldpc_nbp_backward(qldpc_code code, int32_t batch, int32_t T, const float *weights,
+                                const uint32_t *syndromes, const void *workspace,
+                                const float *grad_posteriors, float *grad_weights, void *stream);
+
+/* Inference: neural min-sum with early stop for at most T iterations; the
+ * shots that do not converge are decoded again from scratch with plain
+ * min-sum under `fallback` (FP32, per-shot priors; NULL = no fallback).
+ * used_fallback: device uint8 [batch], out: 1 where the fallback ran.
+ * errors / converged / iters_used describe the returned decode. */
+qldpc_status qldpc_nbp_decode(qldpc_code code, int32_t batch, int32_t T, const float *weights,
+                              const qldpc_decode_params *fallback, const uint32_t *syndromes,
+                              const float *priors, uint32_t *errors, uint8_t *converged,
+                              uint8_t *iters_used, uint8_t *used_fallback, void *stream);
+
 /* Host helper: int8 Q4 prior clamp(round-half-away-from-zero(16 * llr),
  * -127, 127) for `count` values (host arrays). */
 qldpc_status qldpc_quantize_prior(const float *llr, int8_t *out, int64_t count);

@@ -72,6 +72,10 @@ def _load():
         "qldpc_session_destroy": ([vp], i32),
         "qldpc_session_decode": ([vp, i32, vp, vp, vp, vp, vp], i32),
         "qldpc_session_latency": ([vp, i32, i32, i32, vp, vp, vp], i32),
+        "qldpc_nbp_workspace_bytes": ([vp, i32, i32, C.POINTER(C.c_size_t)], i32),
+        "qldpc_nbp_forward": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], i32),
+        "qldpc_nbp_backward": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], i32),
+        "qldpc_nbp_decode": ([vp, i32, i32, vp, C.POINTER(qldpc_decode_params), vp, vp, vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -199,3 +203,29 @@ def qldpc_session_latency(s, nreq: int, batch: int, pool: int, host_syndromes: n
     _check(lib.qldpc_session_latency(s, int(nreq), int(batch), int(pool), _np(host_syndromes),
                                      _np(host_priors), _np(lat)))
     return lat
+
+
+def qldpc_nbp_workspace_bytes(h, batch: int, T: int) -> int:
+    n = C.c_size_t()
+    _check(lib.qldpc_nbp_workspace_bytes(h, int(batch), int(T), C.byref(n)))
+    return int(n.value)
+
+
+def qldpc_nbp_forward(h, batch: int, T: int, weights, syndromes, priors, posteriors, workspace,
+                      stream=None) -> None:
+    _check(lib.qldpc_nbp_forward(h, int(batch), int(T), _ptr(weights), _ptr(syndromes), _ptr(priors),
+                                 _ptr(posteriors), _ptr(workspace), _stream(stream)))
+
+
+def qldpc_nbp_backward(h, batch: int, T: int, weights, syndromes, workspace, grad_posteriors, grad_weights,
+                       stream=None) -> None:
+    _check(lib.qldpc_nbp_backward(h, int(batch), int(T), _ptr(weights), _ptr(syndromes), _ptr(workspace),
+                                  _ptr(grad_posteriors), _ptr(grad_weights), _stream(stream)))
+
+
+def qldpc_nbp_decode(h, batch: int, T: int, weights, fallback, syndromes, priors, errors, converged,
+                     iters_used, used_fallback, stream=None) -> None:
+    fb = None if fallback is None else C.byref(fallback)
+    _check(lib.qldpc_nbp_decode(h, int(batch), int(T), _ptr(weights), fb, _ptr(syndromes), _ptr(priors),
+                                _ptr(errors), _ptr(converged), _ptr(iters_used), _ptr(used_fallback),
+                                _stream(stream)))

@@ -56,6 +56,7 @@ __global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long shot = blockIdx.x;
     const DevCode *__restrict__ code = a.code;
+    if (a.only && a.only[shot] == 0) return;   // uniform over the workgroup
 
     // syndrome bits of the checks this lane owns in each block row
     uint32_t sb[PPL];

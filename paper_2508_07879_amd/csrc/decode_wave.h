@@ -178,7 +178,44 @@ __device__ __forceinline__ int sat127(int x) { return min(127, max(-127, x)); }
 // The decoder body: decodes the 64 / L (or 1) shots starting at shot_base.
 // `lds` points to WaveLds<...>::bytes of this wave's LDS.
 // ---------------------------------------------------------------------------
-template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST>
+// Check rule with per-edge scales (neural min-sum): r_j = sgn_j * fl(w_j *
+// excluded_min_j).
+namespace wave {
+template <int DC>
+__device__ __forceinline__ void cn_f32_weighted(float (&v)[DC], uint32_t P, const float (&wj)[DC]) {
+    float m1 = fminf(fabsf(v[0]), fabsf(v[1]));
+    float m2 = fmaxf(fabsf(v[0]), fabsf(v[1]));
+#pragma unroll
+    for (int j = 2; j < DC; ++j) {
+        m2 = __builtin_amdgcn_fmed3f(m1, m2, fabsf(v[j]));
+        m1 = fminf(m1, fabsf(v[j]));
+    }
+#pragma unroll
+    for (int j = 0; j < DC; ++j) P ^= fbits(v[j]);
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        const float mag = wj[j] * ((fabsf(v[j]) == m1) ? m2 : m1);
+        v[j] = ubits(fbits(mag) | ((P ^ fbits(v[j])) & 0x80000000u));
+    }
+}
+
+// The DC weights of check (R, pos) at iteration k: w[k][(R*L + pos)*DC + j].
+template <int L, int DC>
+__device__ __forceinline__ void load_weights(const float *__restrict__ w, int k, int nnz, int R, int pos,
+                                             float (&wj)[DC]) {
+    const float4 *p = reinterpret_cast<const float4 *>(w + (size_t)k * nnz + (size_t)(R * L + pos) * DC);
+#pragma unroll
+    for (int q = 0; q < DC / 4; ++q) {
+        const float4 x = p[q];
+        wj[4 * q] = x.x;
+        wj[4 * q + 1] = x.y;
+        wj[4 * q + 2] = x.z;
+        wj[4 * q + 3] = x.w;
+    }
+}
+}  // namespace wave
+
+template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED = false>
 __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *__restrict__ code,
                                             long shot_base, int64_t limit, unsigned char *lds) {
     using namespace wave;
@@ -198,7 +235,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     const int g = lane / G::SEG;
     const int p = lane % G::SEG;
     const long shot = shot_base + g;
-    const bool valid = shot < limit;
+    const bool valid = shot < limit && !(a.only && a.only[shot] == 0);
 
     // Syndrome bits of this lane's checks: bit R of sb[h] = s of check R*L + p + 64h.
     uint32_t sb[PPL];
@@ -285,7 +322,13 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                         float v[DC];
 #pragma unroll
                         for (int j = 0; j < DC; ++j) v[j] = msg[(R * DC + j) * ROW + lane + 64 * h];
-                        cn_f32<DC>(v, P, a.alpha);
+                        if constexpr (WEIGHTED) {
+                            float wj[DC];
+                            load_weights<L, DC>(a.weights, k - 1, MB * L * DC, R, p + 64 * h, wj);
+                            cn_f32_weighted<DC>(v, P, wj);
+                        } else {
+                            cn_f32<DC>(v, P, a.alpha);
+                        }
 #pragma unroll
                         for (int j = 0; j < DC; ++j) msg[(R * DC + j) * ROW + lane + 64 * h] = v[j];
                     } else {
@@ -480,12 +523,12 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
 }
 
 // One wave per workgroup; grid = ceil(batch / shots-per-wave).
-template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST>
+template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED = false>
 __global__ __launch_bounds__(64) void k_wave(const DecodeArgs a) {
     using Lay = WaveLds<S, L, FMT, SCHED>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
-    wave_decode<S, L, FMT, SCHED, PER_BIT, POST>(a, a.code, (long)blockIdx.x * Geo<S, L>::SPW,
-                                                 a.batch, lds);
+    wave_decode<S, L, FMT, SCHED, PER_BIT, POST, WEIGHTED>(a, a.code, (long)blockIdx.x * Geo<S, L>::SPW,
+                                                           a.batch, lds);
 }
 
 template <class S, int L, int FMT, int SCHED, bool PB, bool PO>

@@ -28,6 +28,8 @@ struct DecodeArgs {
     float alpha;            // F32
     int32_t alpha_num;      // I8Q4: alpha = alpha_num / 2^alpha_shift
     int32_t alpha_shift;
+    const uint8_t *only;    // nullable: decode only shots with only[shot] != 0
+    const float *weights;   // neural decode: [max_iters][nnz] per-edge scales
 };
 
 struct LaunchKey {

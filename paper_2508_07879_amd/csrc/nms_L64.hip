@@ -1,0 +1,31 @@
+// Instantiations of the neural min-sum kernels for lift size L = 64.
+#include "decode_nms.h"
+
+namespace qldpc {
+
+hipError_t launch_nms_L64(int op, const NmsArgs &n, const DecodeArgs &d, hipStream_t st) {
+    using S = ShapeLP35Z;
+    using G = Geo<S, 64>;
+    switch (op) {
+        case 0:
+            hipLaunchKernelGGL((k_nms_fwd<S, 64>), dim3((unsigned)n.tiles), dim3(64), 0, st, n);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_nms_bwd<S, 64>), dim3((unsigned)n.waves), dim3(64), 0, st, n);
+            break;
+        case 2: {
+            const long total = (long)n.T * S::SLOTS * 64;
+            hipLaunchKernelGGL((k_nms_reduce<S, 64>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n);
+            break;
+        }
+        case 3:
+            hipLaunchKernelGGL((k_wave<S, 64, 0, 0, false, false, true>),
+                               dim3((unsigned)((d.batch + G::SPW - 1) / G::SPW)), dim3(64), 0, st, d);
+            break;
+        default:
+            return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qldpc
