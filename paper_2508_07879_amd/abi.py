@@ -50,6 +50,14 @@ class qldpc_decode_params(C.Structure):
 
 
 def _load():
+    # torch loads its own HIP runtime under the unversioned file name; let it
+    # initialise first so that libqldpc.so binds to that same runtime (same
+    # soname) instead of bringing a second one into the process.
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_07879_amd.build` "
                           "(the decoder has no CPU fallback)")

@@ -1,0 +1,169 @@
+"""Train neural min-sum weights and compare logical error rates with plain
+min-sum at equal and larger iteration budgets.
+
+Training data are (error, syndrome) pairs drawn from the same iid X-flip
+noise the decoder is evaluated on, from a seed range disjoint from the
+evaluation shots.  Loss: BCE between the true error bits and sigma(-Q),
+averaged over all T iterations (see nms.bce_loss).  Optimiser: Adam.
+
+    python -m paper_2508_07879_amd.train_nms --L 64 --p 0.05 --T 16 \
+        --train-shots 1048576 --batch 4096 --epochs 4 --eval-shots 262144 \
+        --out weights.pt --json results.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def _batches(side, seed, shots, p, chunk):
+    from workload import noise
+    for lo in range(0, shots, chunk):
+        yield noise.Batch(side, seed, np.arange(lo, min(shots, lo + chunk)), p)
+
+
+def logical_fail_counts(lam_t, e_true_bits, err_words, conv, n):
+    """Failures on the device: residual (e xor e_hat) against the logical
+    basis as a 0/1 matrix product, parity = count mod 2."""
+    import torch
+    w = err_words.to(torch.int64) & 0xFFFFFFFF
+    shifts = torch.arange(32, device=w.device, dtype=torch.int64)
+    e_hat = ((w.unsqueeze(-1) >> shifts) & 1).reshape(w.shape[0], -1)[:, :n]
+    rho = (e_hat ^ e_true_bits.to(torch.int64)).to(torch.float32)
+    par = torch.remainder(rho @ lam_t, 2.0)
+    flips = par.sum(dim=1) > 0
+    return int((flips | (conv == 0)).sum().item())
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--L", type=int, default=64)
+    ap.add_argument("--p", type=float, default=0.05)
+    ap.add_argument("--T", type=int, default=16)
+    ap.add_argument("--train-shots", type=int, default=1 << 20)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-shots", type=int, default=1 << 18)
+    ap.add_argument("--train-seed", type=int, default=1_000_003)
+    ap.add_argument("--eval-seed", type=int, default=2_000_003)
+    ap.add_argument("--out", default="")
+    ap.add_argument("--json", default="")
+    args = ap.parse_args(argv)
+
+    import torch
+
+    from paper_2508_07879_amd import Decoder, abi, nms
+    from workload import bits, gf2, lp
+
+    dev = torch.device("cuda", 0)
+    code = lp.lp_code(args.L)
+    side = code.hz
+    dec = Decoder(side)
+    T = args.T
+    report = dict(L=args.L, n=side.n, p=args.p, T=T, batch=args.batch, lr=args.lr, epochs=args.epochs,
+                  train_shots=args.train_shots, eval_shots=args.eval_shots)
+
+    # ---- training data, resident on the device -----------------------------
+    t0 = time.time()
+    syn_all, pr_all, e_all = [], [], []
+    for b in _batches(side, args.train_seed, args.train_shots, args.p, 65536):
+        syn_all.append(torch.from_numpy(bits.pack_bits(b.s).view(np.int32)).to(dev))
+        pr_all.append(torch.from_numpy(b.gamma).to(dev))
+        e_all.append(torch.from_numpy(b.e).to(dev))
+    syn_all, pr_all, e_all = torch.cat(syn_all), torch.cat(pr_all), torch.cat(e_all)
+    report["train_data_s"] = time.time() - t0
+    print(f"training data: {args.train_shots} shots in {report['train_data_s']:.1f} s", flush=True)
+
+    w = nms.init_weights(T, side.nnz, 0.75, device=dev).requires_grad_(True)
+    opt = torch.optim.Adam([w], lr=args.lr)
+    steps = args.train_shots // args.batch
+    losses = []
+    t0 = time.time()
+    gen = torch.Generator(device="cpu").manual_seed(args.train_seed)
+    for ep in range(args.epochs):
+        perm = torch.randperm(args.train_shots, generator=gen).to(dev)
+        ep_loss = 0.0
+        for s in range(steps):
+            idx = perm[s * args.batch:(s + 1) * args.batch]
+            post = nms.NeuralMinSum.apply(dec, w, syn_all[idx].contiguous(), pr_all[idx].contiguous())
+            loss = nms.bce_loss(post, e_all[idx].to(torch.float32))
+            opt.zero_grad(set_to_none=True)
+            loss.backward()
+            opt.step()
+            ep_loss += float(loss.detach())
+        losses.append(ep_loss / steps)
+        print(f"epoch {ep}: mean loss {losses[-1]:.6f}", flush=True)
+    torch.cuda.synchronize()
+    report["train_s"] = time.time() - t0
+    report["loss_per_epoch"] = losses
+    if args.out:
+        nms.save_weights(args.out, w, side, meta=report, optimizer=opt)
+    del syn_all, pr_all, e_all
+
+    # ---- evaluation on held-out shots ---------------------------------------
+    lam = gf2.logical_basis(code.hx.dense(), side.dense())
+    lam_t = torch.from_numpy(lam.T.astype(np.float32)).to(dev)
+    wd = w.detach().contiguous()
+    alpha_w = nms.init_weights(T, side.nnz, 0.75, device=dev)
+    configs = []
+    for t in sorted({max(1, T // 4), T // 2, (3 * T) // 4, T}):
+        configs.append((f"nms_T{t}", "nms", t, True))
+        configs.append((f"nms_T{t}_nofallback", "nms", t, False))
+    configs += [("ms_16", "ms", 16, False), ("ms_32", "ms", 32, False)]
+    for t in sorted({max(1, T // 4), T // 2, (3 * T) // 4}):
+        configs.append((f"ms_{t}", "ms", t, False))
+    stats = {name: dict(fails=0, shots=0, iters=0, fallback=0, ms=0.0) for name, *_ in configs}
+    for b in _batches(side, args.eval_seed, args.eval_shots, args.p, 65536):
+        B = b.B
+        syn = torch.from_numpy(bits.pack_bits(b.s).view(np.int32)).to(dev)
+        pr = torch.from_numpy(b.gamma).to(dev)
+        et = torch.from_numpy(b.e).to(dev)
+        err, conv, it, _ = dec.outputs(B)
+        used = torch.zeros(B, dtype=torch.uint8, device=dev)
+        for name, kind, t, fb in configs:
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            if kind == "nms":
+                fbp = dec.params(max_iters=32, layout=abi.QLDPC_LAYOUT_WAVE) if fb else None
+                abi.qldpc_nbp_decode(dec.handle, B, t, wd[:t].contiguous(), fbp, syn, pr, err, conv, it, used)
+            else:
+                prm = dec.params(max_iters=t, layout=abi.QLDPC_LAYOUT_WAVE)
+                abi.qldpc_decode_batch(dec.handle, prm, B, syn, pr, err, conv, it, None)
+            ev1.record()
+            torch.cuda.synchronize()
+            st = stats[name]
+            st["ms"] += ev0.elapsed_time(ev1)
+            st["fails"] += logical_fail_counts(lam_t, et, err, conv, side.n)
+            st["shots"] += B
+            st["iters"] += int(it.to(torch.int64).sum().item())
+            if kind == "nms":
+                st["fallback"] += int(used.to(torch.int64).sum().item())
+    res = {}
+    for name, st in stats.items():
+        lo, hi = gf2.wilson(st["fails"], st["shots"])
+        res[name] = dict(ler=st["fails"] / st["shots"], ci95=[lo, hi], mean_iters=st["iters"] / st["shots"],
+                         fallback_rate=st["fallback"] / st["shots"],
+                         syndromes_per_s=st["shots"] / (st["ms"] * 1e-3))
+        print(f"{name:22s} LER {res[name]['ler']:.5f} [{lo:.5f}, {hi:.5f}]  mean iters "
+              f"{res[name]['mean_iters']:.2f}  fallback {res[name]['fallback_rate']:.4f}  "
+              f"{res[name]['syndromes_per_s']:.3g} syn/s", flush=True)
+    report["eval"] = res
+    del alpha_w
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump(report, f, indent=1)
+    return report
+
+
+if __name__ == "__main__":
+    main()
