@@ -222,6 +222,44 @@ qldpc_status qldpc_session_latency(qldpc_session s, int32_t nreq, int32_t batch,
                                    double *lat_us);
 
 /* ------------------------------------------------------------------------ */
+/* Mixed-code persistent batches: shots of several lifted codes (L in        */
+/* {16, 32, 64, 128}, H_Z pattern) with per-shot priors decoded in one       */
+/* persistent launch (batching of many decoders, Table 1 "asynchronous      */
+/* kernel execution"; each shot follows Algorithm 1 on its own code).       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct qldpc_mixed_s *qldpc_mixed;
+
+/* Plan over 1..8 code objects on one device for batches of up to
+ * max_batch shots (FP32 flooding, per-shot priors; params gives alpha,
+ * iterations and early stop).  Allocates 4 * (max_batch + 17) bytes of
+ * device scratch.  use_graph = 1: every distinct argument set is captured
+ * once as a hipGraph (bucketing kernels + persistent decoder) and replayed. */
+qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const qldpc_decode_params *params,
+                                int32_t max_batch, int32_t use_graph, qldpc_mixed *out);
+qldpc_status qldpc_mixed_destroy(qldpc_mixed plan);
+
+/* Shot i belongs to code shot_code[i] (device int32 [batch], index into the
+ * plan's codes; other values leave the shot untouched); its packed syndrome
+ * starts at syndromes + syn_off[i] words and its error estimate is written
+ * at errors + err_off[i] words (device int64 [batch] each; the caller
+ * guarantees ceil(m/32) and ceil(n/32) words of room).  priors: device float
+ * [batch]; converged / iters_used: device uint8 [batch].  A shot's result
+ * equals qldpc_decode_batch of that shot alone.  Calls on one plan must not
+ * overlap (the scratch is shared). */
+qldpc_status qldpc_mixed_decode(qldpc_mixed plan, int32_t batch, const int32_t *shot_code,
+                                const int64_t *syn_off, const int64_t *err_off, const uint32_t *syndromes,
+                                const float *priors, uint32_t *errors, uint8_t *converged,
+                                uint8_t *iters_used, void *stream);
+
+/* Times the persistent grid at 2, 4, 8 and 16 wavefronts per compute unit
+ * on the caller's batch, keeps the fastest in the plan and returns it. */
+qldpc_status qldpc_mixed_autotune(qldpc_mixed plan, int32_t batch, const int32_t *shot_code,
+                                  const int64_t *syn_off, const int64_t *err_off, const uint32_t *syndromes,
+                                  const float *priors, uint32_t *errors, uint8_t *converged,
+                                  uint8_t *iters_used, void *stream, int32_t *best_waves);
+
+/* ------------------------------------------------------------------------ */
 /* Neural min-sum: flooding min-sum whose check rule scales edge e at        */
 /* iteration k by a learned weight w[k][e] instead of alpha (Section 2,      */
 /* Algorithm 1, check-node update, with alpha generalised per edge and       */

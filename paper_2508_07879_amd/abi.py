@@ -80,6 +80,10 @@ def _load():
         "qldpc_session_destroy": ([vp], i32),
         "qldpc_session_decode": ([vp, i32, vp, vp, vp, vp, vp], i32),
         "qldpc_session_latency": ([vp, i32, i32, i32, vp, vp, vp], i32),
+        "qldpc_mixed_create": ([C.POINTER(vp), i32, C.POINTER(qldpc_decode_params), i32, i32, C.POINTER(vp)], i32),
+        "qldpc_mixed_destroy": ([vp], i32),
+        "qldpc_mixed_decode": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+        "qldpc_mixed_autotune": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32)], i32),
         "qldpc_nbp_workspace_bytes": ([vp, i32, i32, C.POINTER(C.c_size_t)], i32),
         "qldpc_nbp_forward": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], i32),
         "qldpc_nbp_backward": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], i32),
@@ -237,3 +241,30 @@ def qldpc_nbp_decode(h, batch: int, T: int, weights, fallback, syndromes, priors
     _check(lib.qldpc_nbp_decode(h, int(batch), int(T), _ptr(weights), fb, _ptr(syndromes), _ptr(priors),
                                 _ptr(errors), _ptr(converged), _ptr(iters_used), _ptr(used_fallback),
                                 _stream(stream)))
+
+
+def qldpc_mixed_create(handles, params: qldpc_decode_params, max_batch: int, use_graph: bool = True):
+    arr = (C.c_void_p * len(handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    x = C.c_void_p()
+    _check(lib.qldpc_mixed_create(arr, len(handles), C.byref(params), int(max_batch), int(bool(use_graph)),
+                                  C.byref(x)))
+    return x
+
+
+def qldpc_mixed_destroy(x) -> None:
+    _check(lib.qldpc_mixed_destroy(x))
+
+
+def qldpc_mixed_decode(x, batch: int, shot_code, syn_off, err_off, syndromes, priors, errors, converged,
+                       iters_used=None, stream=None) -> None:
+    _check(lib.qldpc_mixed_decode(x, int(batch), _ptr(shot_code), _ptr(syn_off), _ptr(err_off), _ptr(syndromes),
+                                  _ptr(priors), _ptr(errors), _ptr(converged), _ptr(iters_used), _stream(stream)))
+
+
+def qldpc_mixed_autotune(x, batch: int, shot_code, syn_off, err_off, syndromes, priors, errors, converged,
+                         iters_used=None, stream=None) -> int:
+    w = C.c_int32()
+    _check(lib.qldpc_mixed_autotune(x, int(batch), _ptr(shot_code), _ptr(syn_off), _ptr(err_off), _ptr(syndromes),
+                                    _ptr(priors), _ptr(errors), _ptr(converged), _ptr(iters_used), _stream(stream),
+                                    C.byref(w)))
+    return int(w.value)

@@ -55,17 +55,19 @@ template <int FMT> struct Fmt;
 template <> struct Fmt<0> { using msg_t = float; using q_t = float; using prior_t = float; };
 template <> struct Fmt<1> { using msg_t = int8_t; using q_t = int16_t; using prior_t = int8_t; };
 
-template <class S, int L, int FMT, int SCHED>
+template <class S, int L, int FMT, int SCHED, int NG = 1>
 struct WaveLds {
     using G = Geo<S, L>;
     using msg_t = typename Fmt<FMT>::msg_t;
     using q_t = typename Fmt<FMT>::q_t;
-    static constexpr int MSG = S::SLOTS * G::ROW;
-    static constexpr int QN = SCHED == 1 ? S::NB * G::ROW : 0;
+    static constexpr int H = L <= 64 ? NG : L / 64;
+    static constexpr int ROW = 64 * H;
+    static constexpr int MSG = S::SLOTS * ROW;
+    static constexpr int QN = SCHED == 1 ? S::NB * ROW : 0;
     static constexpr size_t msg_bytes = MSG * sizeof(msg_t);
     static constexpr size_t q_off = (msg_bytes + 15) & ~size_t(15);
     static constexpr size_t e_off = (q_off + QN * sizeof(q_t) + 15) & ~size_t(15);
-    static constexpr size_t bytes = e_off + G::SPW * G::EW * 4;
+    static constexpr size_t bytes = e_off + (L <= 64 ? NG : 1) * G::SPW * G::EW * 4;
 };
 
 namespace wave {
@@ -215,17 +217,34 @@ __device__ __forceinline__ void load_weights(const float *__restrict__ w, int k,
 }
 }  // namespace wave
 
-template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED = false>
+// One 64-lane group of a wavefront: the shot it decodes (-1 = none) and
+// where that shot's packed syndrome and error words live.
+struct ShotRef {
+    long shot;
+    const uint32_t *syn;
+    uint32_t *err;
+};
+
+// ---------------------------------------------------------------------------
+// The decoder body.  A lane owns H "halves": for L = 128 the two circulant
+// rows t and t + 64 of one shot; for L <= 64, NG independent 64-lane groups,
+// each decoding its own 64 / L shots (ref[h] describes group h's segment of
+// this lane).  `lds` points to WaveLds<S, L, FMT, SCHED, NG>::bytes.
+// ---------------------------------------------------------------------------
+template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED, int NG>
 __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *__restrict__ code,
-                                            long shot_base, int64_t limit, unsigned char *lds) {
+                                            const ShotRef (&ref)[NG], unsigned char *lds) {
     using namespace wave;
     using G = Geo<S, L>;
-    using Lay = WaveLds<S, L, FMT, SCHED>;
+    using Lay = WaveLds<S, L, FMT, SCHED, NG>;
     using msg_t = typename Fmt<FMT>::msg_t;
     using q_t = typename Fmt<FMT>::q_t;
     using prior_t = typename Fmt<FMT>::prior_t;
     using acc_t = typename std::conditional<FMT == 0, float, int>::type;
-    constexpr int MB = S::MB, NB = S::NB, DC = S::DC, PPL = G::PPL, ROW = G::ROW;
+    static_assert(L <= 64 || NG == 1, "L = 128 uses both halves for one shot");
+    constexpr bool GRP = L <= 64;                 // halves are independent groups
+    constexpr int H = GRP ? NG : L / 64;          // halves per lane
+    constexpr int MB = S::MB, NB = S::NB, DC = S::DC, ROW = 64 * H;
 
     msg_t *msg = reinterpret_cast<msg_t *>(lds);
     q_t *Qs = reinterpret_cast<q_t *>(lds + Lay::q_off);
@@ -234,43 +253,61 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     const int lane = threadIdx.x & 63;
     const int g = lane / G::SEG;
     const int p = lane % G::SEG;
-    const long shot = shot_base + g;
-    const bool valid = shot < limit && !(a.only && a.only[shot] == 0);
+    auto grp = [](int h) { return GRP ? h : 0; };
+    auto posoff = [](int h) { return GRP ? 0 : 64 * h; };   // circulant row offset of half h
+    // LDS row index of the entry that variable position (lane, half h)
+    // reaches through a block of shift s (check = var - s), and back.
+    auto vn_at = [&](int h, uint32_t s) -> int {
+        if constexpr (GRP) return 64 * h + ((int)(((uint32_t)lane - s) & (uint32_t)(L - 1)) | (lane & ~(L - 1)));
+        else return (int)(((uint32_t)(lane + 64 * h) - s) & (uint32_t)(L - 1));
+    };
+    auto cn_at = [&](int h, uint32_t s) -> int {
+        if constexpr (GRP) return 64 * h + ((int)(((uint32_t)lane + s) & (uint32_t)(L - 1)) | (lane & ~(L - 1)));
+        else return (int)(((uint32_t)(lane + 64 * h) + s) & (uint32_t)(L - 1));
+    };
 
-    // Syndrome bits of this lane's checks: bit R of sb[h] = s of check R*L + p + 64h.
-    uint32_t sb[PPL];
+    bool valid[NG];
 #pragma unroll
-    for (int h = 0; h < PPL; ++h) {
+    for (int q = 0; q < NG; ++q)
+        valid[q] = ref[q].shot >= 0 && !(a.only && a.only[ref[q].shot] == 0);
+
+    // Syndrome bits of this lane's checks: bit R of sb[h] = s of check R*L + p + posoff(h).
+    uint32_t sb[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
         sb[h] = 0;
-        if (valid) {
+        if (valid[grp(h)]) {
 #pragma unroll
             for (int R = 0; R < MB; ++R) {
-                const int m = R * L + p + 64 * h;
-                const uint32_t w = a.syn[shot * G::SW + (m >> 5)];
+                const int m = R * L + p + posoff(h);
+                const uint32_t w = ref[grp(h)].syn[m >> 5];
                 sb[h] |= ((w >> (m & 31)) & 1u) << R;
             }
         }
     }
     // Priors (FP32 canonicalised so that no message is -0.0).
-    acc_t gam[PER_BIT ? NB * PPL : 1];
+    acc_t gam[PER_BIT ? NB * H : NG];
     {
         const prior_t *pr = static_cast<const prior_t *>(a.prior);
         if constexpr (PER_BIT) {
 #pragma unroll
             for (int C = 0; C < NB; ++C)
 #pragma unroll
-                for (int h = 0; h < PPL; ++h) {
-                    acc_t v = valid ? (acc_t)pr[shot * G::N + C * L + p + 64 * h] : (acc_t)1;
+                for (int h = 0; h < H; ++h) {
+                    acc_t v = valid[grp(h)] ? (acc_t)pr[ref[grp(h)].shot * G::N + C * L + p + posoff(h)] : (acc_t)1;
                     if constexpr (FMT == 0) v = v + 0.0f;
-                    gam[C * PPL + h] = v;
+                    gam[C * H + h] = v;
                 }
         } else {
-            acc_t v = valid ? (acc_t)pr[shot] : (acc_t)1;
-            if constexpr (FMT == 0) v = v + 0.0f;
-            gam[0] = v;
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+                acc_t v = valid[q] ? (acc_t)pr[ref[q].shot] : (acc_t)1;
+                if constexpr (FMT == 0) v = v + 0.0f;
+                gam[q] = v;
+            }
         }
     }
-    auto gamma_of = [&](int C, int h) -> acc_t { return PER_BIT ? gam[C * PPL + h] : gam[0]; };
+    auto gamma_of = [&](int C, int h) -> acc_t { return PER_BIT ? gam[C * H + h] : gam[grp(h)]; };
 
     // Initial state.  Flooding: q^(0) = gamma on every edge.  Layered: r = 0,
     // Q = gamma.
@@ -282,41 +319,42 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                 constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
                 const uint32_t s = (uint32_t)code->shift[slot];
 #pragma unroll
-                for (int h = 0; h < PPL; ++h)
-                    msg[slot * ROW + vn_index<L>(lane, h, s)] = (msg_t)gamma_of(C, h);
+                for (int h = 0; h < H; ++h) msg[slot * ROW + vn_at(h, s)] = (msg_t)gamma_of(C, h);
             });
         });
     } else {
 #pragma unroll
         for (int sl = 0; sl < S::SLOTS; ++sl)
 #pragma unroll
-            for (int h = 0; h < PPL; ++h) msg[sl * ROW + lane + 64 * h] = (msg_t)0;
+            for (int h = 0; h < H; ++h) msg[sl * ROW + lane + 64 * h] = (msg_t)0;
 #pragma unroll
         for (int C = 0; C < NB; ++C)
 #pragma unroll
-            for (int h = 0; h < PPL; ++h) Qs[C * ROW + lane + 64 * h] = (q_t)gamma_of(C, h);
+            for (int h = 0; h < H; ++h) Qs[C * ROW + lane + 64 * h] = (q_t)gamma_of(C, h);
     }
 
-    acc_t Qr[POST ? NB * PPL : 1];
-    uint64_t eb[PPL];
-    bool done = !valid;
+    acc_t Qr[POST ? NB * H : 1];
+    uint64_t eb[H];
+    bool done[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) done[q] = !valid[q];
 
     for (int k = 1; k <= a.max_iters; ++k) {
         __builtin_amdgcn_wave_barrier();
-        uint64_t acc[MB][PPL];
+        uint64_t acc[MB][H];
 #pragma unroll
         for (int R = 0; R < MB; ++R)
 #pragma unroll
-            for (int h = 0; h < PPL; ++h) acc[R][h] = ballot(((sb[h] >> R) & 1u) != 0);
+            for (int h = 0; h < H; ++h) acc[R][h] = ballot(((sb[h] >> R) & 1u) != 0);
 #pragma unroll
-        for (int h = 0; h < PPL; ++h) eb[h] = 0;
+        for (int h = 0; h < H; ++h) eb[h] = 0;
 
         if constexpr (SCHED == 0) {
             // ---------------- check-node pass --------------------------------
 #pragma unroll
             for (int R = 0; R < MB; ++R) {
 #pragma unroll
-                for (int h = 0; h < PPL; ++h) {
+                for (int h = 0; h < H; ++h) {
                     const uint32_t P = sb[h] << (31 - R);
                     if constexpr (FMT == 0) {
                         float v[DC];
@@ -324,7 +362,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                         for (int j = 0; j < DC; ++j) v[j] = msg[(R * DC + j) * ROW + lane + 64 * h];
                         if constexpr (WEIGHTED) {
                             float wj[DC];
-                            load_weights<L, DC>(a.weights, k - 1, MB * L * DC, R, p + 64 * h, wj);
+                            load_weights<L, DC>(a.weights, k - 1, MB * L * DC, R, p + posoff(h), wj);
                             cn_f32_weighted<DC>(v, P, wj);
                         } else {
                             cn_f32<DC>(v, P, a.alpha);
@@ -348,7 +386,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
             static_for<0, MB>([&](auto Rc) {
                 constexpr int R = decltype(Rc)::value;
 #pragma unroll
-                for (int h = 0; h < PPL; ++h) {
+                for (int h = 0; h < H; ++h) {
                     const uint32_t P = sb[h] << (31 - R);
                     int qi[DC];
                     acc_t v[DC], rold[DC];
@@ -356,7 +394,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                         constexpr int j = decltype(Jc)::value;
                         constexpr int C = S::T.slot_bc[R][j];
                         const uint32_t s = (uint32_t)code->shift[R * DC + j];
-                        qi[j] = C * ROW + cn_index<L>(lane, h, s);
+                        qi[j] = C * ROW + cn_at(h, s);
                         rold[j] = (acc_t)msg[(R * DC + j) * ROW + lane + 64 * h];
                     });
                     if constexpr (FMT == 0) {
@@ -394,9 +432,9 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
         static_for<0, NB>([&](auto Cc) {
             constexpr int C = decltype(Cc)::value;
             constexpr int d = S::T.col_deg[C];
-            uint64_t mask[PPL];
+            uint64_t mask[H];
 #pragma unroll
-            for (int h = 0; h < PPL; ++h) {
+            for (int h = 0; h < H; ++h) {
                 acc_t Q;
                 if constexpr (SCHED == 0) {
                     acc_t r[d];
@@ -404,7 +442,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                     static_for<0, d>([&](auto Ii) {
                         constexpr int i = decltype(Ii)::value;
                         constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
-                        idx[i] = slot * ROW + vn_index<L>(lane, h, (uint32_t)code->shift[slot]);
+                        idx[i] = slot * ROW + vn_at(h, (uint32_t)code->shift[slot]);
                         r[i] = (acc_t)msg[idx[i]];
                     });
                     if constexpr (FMT == 0) {
@@ -433,7 +471,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                 } else {
                     Q = (acc_t)Qs[C * ROW + lane + 64 * h];
                 }
-                if constexpr (POST) Qr[C * PPL + h] = Q;
+                if constexpr (POST) Qr[C * H + h] = Q;
                 const bool e = Q < (acc_t)0;
                 eb[h] |= (uint64_t)e << C;
                 mask[h] = ballot(e);
@@ -444,91 +482,114 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                 constexpr int R = S::T.col_R[C][i];
                 constexpr int slot = R * DC + S::T.col_j[C][i];
                 const uint32_t s = (uint32_t)code->shift[slot];
-                if constexpr (L <= 64) {
-                    acc[R][0] ^= seg_rotr<L>(mask[0], s, code->lowmask[slot]);
+                if constexpr (GRP) {
+#pragma unroll
+                    for (int h = 0; h < H; ++h) acc[R][h] ^= seg_rotr<L>(mask[h], s, code->lowmask[slot]);
                 } else {
                     uint64_t lo, hi;
-                    rotr128(mask[0], mask[PPL - 1], s, lo, hi);
+                    rotr128(mask[0], mask[H - 1], s, lo, hi);
                     acc[R][0] ^= lo;
-                    acc[R][PPL - 1] ^= hi;
+                    acc[R][H - 1] ^= hi;
                 }
             });
         });
 
-        // ---------------- stopping rule --------------------------------------
-        uint64_t uns[PPL];
+        // ---------------- stopping rule, outputs ------------------------------
+        uint64_t uns[H];
 #pragma unroll
-        for (int h = 0; h < PPL; ++h) {
+        for (int h = 0; h < H; ++h) {
             uns[h] = 0;
 #pragma unroll
             for (int R = 0; R < MB; ++R) uns[h] |= acc[R][h];
         }
-        bool my_unsat;
-        if constexpr (L < 64) {
-            my_unsat = ((uns[0] >> (g * L)) & G::SEGMASK) != 0;
-        } else if constexpr (L == 64) {
-            my_unsat = uns[0] != 0;
-        } else {
-            my_unsat = (uns[0] | uns[PPL - 1]) != 0;
+        bool conv_now[NG], emit_me[NG];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            bool unsat;
+            if constexpr (L < 64) unsat = ((uns[q] >> (g * L)) & G::SEGMASK) != 0;
+            else if constexpr (L == 64) unsat = uns[q] != 0;
+            else unsat = (uns[0] | uns[H - 1]) != 0;
+            conv_now[q] = !unsat;
+            emit_me[q] = !done[q] && ((a.early_stop && conv_now[q]) || k == a.max_iters);
+            any = any || emit_me[q];
         }
-        const bool conv_now = !my_unsat;
-        const bool emit_me = !done && ((a.early_stop && conv_now) || k == a.max_iters);
-        if (ballot(emit_me)) {
-            // stage the packed decisions of every shot of the wave in LDS
-            __builtin_amdgcn_wave_barrier();
+        if (ballot(any)) {
 #pragma unroll
-            for (int C = 0; C < NB; ++C) {
+            for (int q = 0; q < NG; ++q) {
+                if (!ballot(emit_me[q])) continue;
+                // stage the packed decisions of group q's shots in LDS
+                uint32_t *eq = ebuf + q * (G::SPW * G::EW);
+                __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                for (int h = 0; h < PPL; ++h) {
-                    const uint64_t m = ballot(((eb[h] >> C) & 1ull) != 0);
-                    if constexpr (L == 16) {
-                        if (lane < 4)
-                            reinterpret_cast<uint16_t *>(ebuf)[lane * G::EW * 2 + C] =
-                                (uint16_t)(m >> (16 * lane));
-                    } else if constexpr (L == 32) {
-                        if (lane < 2) ebuf[lane * G::EW + C] = (uint32_t)(m >> (32 * lane));
-                    } else if constexpr (L == 64) {
-                        if (lane < 2) ebuf[2 * C + lane] = (uint32_t)(m >> (32 * lane));
+                for (int C = 0; C < NB; ++C) {
+                    if constexpr (GRP) {
+                        const uint64_t m = ballot(((eb[q] >> C) & 1ull) != 0);
+                        if constexpr (L == 16) {
+                            if (lane < 4)
+                                reinterpret_cast<uint16_t *>(eq)[lane * G::EW * 2 + C] = (uint16_t)(m >> (16 * lane));
+                        } else if constexpr (L == 32) {
+                            if (lane < 2) eq[lane * G::EW + C] = (uint32_t)(m >> (32 * lane));
+                        } else {
+                            if (lane < 2) eq[2 * C + lane] = (uint32_t)(m >> (32 * lane));
+                        }
                     } else {
-                        if (lane < 2) ebuf[4 * C + 2 * h + lane] = (uint32_t)(m >> (32 * lane));
+#pragma unroll
+                        for (int h = 0; h < H; ++h) {
+                            const uint64_t m = ballot(((eb[h] >> C) & 1ull) != 0);
+                            if (lane < 2) eq[4 * C + 2 * h + lane] = (uint32_t)(m >> (32 * lane));
+                        }
                     }
                 }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (emit_me) {
-                for (int w = p; w < G::EW; w += G::SEG) a.err[shot * G::EW + w] = ebuf[g * G::EW + w];
-                if (p == 0) {
-                    a.conv[shot] = conv_now ? 1 : 0;
-                    if (a.iters) a.iters[shot] = (uint8_t)k;
-                }
-                if constexpr (POST) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (emit_me[q]) {
+                    const long shot = ref[q].shot;
+                    for (int w = p; w < G::EW; w += G::SEG) ref[q].err[w] = eq[g * G::EW + w];
+                    if (p == 0) {
+                        a.conv[shot] = conv_now[q] ? 1 : 0;
+                        if (a.iters) a.iters[shot] = (uint8_t)k;
+                    }
+                    if constexpr (POST) {
 #pragma unroll
-                    for (int C = 0; C < NB; ++C)
+                        for (int C = 0; C < NB; ++C)
 #pragma unroll
-                        for (int h = 0; h < PPL; ++h) {
-                            float qv;
-                            if constexpr (FMT == 0) qv = Qr[C * PPL + h];
-                            else qv = (float)Qr[C * PPL + h] * 0.0625f;
-                            a.post[shot * G::N + C * L + p + 64 * h] = qv;
-                        }
+                            for (int h = 0; h < H; ++h) {
+                                if (grp(h) != q) continue;
+                                float qv;
+                                if constexpr (FMT == 0) qv = Qr[C * H + h];
+                                else qv = (float)Qr[C * H + h] * 0.0625f;
+                                a.post[shot * G::N + C * L + p + posoff(h)] = qv;
+                            }
+                    }
                 }
+                __builtin_amdgcn_wave_barrier();
             }
-            __builtin_amdgcn_wave_barrier();
         }
-        done = done || emit_me;
-        if (ballot(!done) == 0) break;
+        bool alldone = true;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            done[q] = done[q] || emit_me[q];
+            alldone = alldone && done[q];
+        }
+        if (ballot(!alldone) == 0) break;
     }
 }
 
 // One wave per workgroup; grid = ceil(batch / shots-per-wave).
 template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED = false>
 __global__ __launch_bounds__(64) void k_wave(const DecodeArgs a) {
-    using Lay = WaveLds<S, L, FMT, SCHED>;
+    using G = Geo<S, L>;
+    using Lay = WaveLds<S, L, FMT, SCHED, 1>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
-    wave_decode<S, L, FMT, SCHED, PER_BIT, POST, WEIGHTED>(a, a.code, (long)blockIdx.x * Geo<S, L>::SPW,
-                                                           a.batch, lds);
+    const int g = (threadIdx.x & 63) / G::SEG;
+    const long shot = (long)blockIdx.x * G::SPW + g;
+    ShotRef ref[1];
+    ref[0].shot = shot < a.batch ? shot : -1;
+    ref[0].syn = a.syn + (shot < a.batch ? shot : 0) * G::SW;
+    ref[0].err = a.err + (shot < a.batch ? shot : 0) * G::EW;
+    wave_decode<S, L, FMT, SCHED, PER_BIT, POST, WEIGHTED, 1>(a, a.code, ref, lds);
 }
 
 template <class S, int L, int FMT, int SCHED, bool PB, bool PO>

@@ -1,0 +1,213 @@
+// Mixed-code persistent decoder: launch sequence and C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+
+#include "decode_mixed.h"
+#include "internal.h"
+
+using namespace qldpc;
+
+struct qldpc_mixed_s {
+    int32_t ncodes = 0, max_batch = 0, use_graph = 0, device = 0;
+    qldpc_code codes[kMaxMixCodes] = {};
+    qldpc_decode_params params{};
+    int32_t waves = 0;              // persistent grid size
+    int32_t *scratch = nullptr;     // device
+    std::mutex mu;
+    std::map<std::tuple<int32_t, const void *, const void *, const void *, const void *, const void *, const void *,
+                        const void *, const void *, const void *, void *, int32_t>,
+             hipGraphExec_t>
+        graphs;
+};
+
+namespace {
+
+qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, const int64_t *syn_off,
+                     const int64_t *err_off, const uint32_t *syn, const float *prior, uint32_t *err, uint8_t *conv,
+                     uint8_t *iters, hipStream_t st, int32_t waves) {
+    MixedArgs m{};
+    m.base.alpha = x->params.alpha;
+    m.base.max_iters = x->params.max_iters;
+    m.base.early_stop = x->params.early_stop ? 1 : 0;
+    m.base.prior = prior;
+    m.base.conv = conv;
+    m.base.iters = iters;
+    m.base.batch = batch;
+    m.ncodes = x->ncodes;
+    for (int c = 0; c < x->ncodes; ++c) {
+        m.codes[c] = x->codes[c]->dev;
+        m.L[c] = x->codes[c]->L;
+    }
+    // bucket order: largest L first, then code index
+    for (int c = 0; c < x->ncodes; ++c) {
+        int r = 0;
+        for (int d = 0; d < x->ncodes; ++d)
+            if (m.L[d] > m.L[c] || (m.L[d] == m.L[c] && d < c)) ++r;
+        m.rank[c] = r;
+    }
+    m.shot_code = shot_code;
+    m.syn_off = syn_off;
+    m.err_off = err_off;
+    m.syn = syn;
+    m.err = err;
+    m.scratch = x->scratch;
+    m.batch = batch;
+    const unsigned nb = (unsigned)((batch + 255) / 256);
+    hipLaunchKernelGGL(k_mix_clear, dim3(1), dim3(64), 0, st, m);
+    hipLaunchKernelGGL(k_mix_count, dim3(nb), dim3(256), 0, st, m);
+    hipLaunchKernelGGL(k_mix_scatter, dim3(nb), dim3(256), 0, st, m);
+    hipLaunchKernelGGL(k_mix_decode<ShapeLP35Z>, dim3((unsigned)waves), dim3(64), 0, st, m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "mixed_decode: launch");
+    return QLDPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const qldpc_decode_params *params,
+                                int32_t max_batch, int32_t use_graph, qldpc_mixed *out) {
+    if (!codes || !params || !out) return set_error(QLDPC_ERR_INVALID_ARG, "mixed_create: null argument");
+    if (ncodes < 1 || ncodes > kMaxMixCodes) return set_error(QLDPC_ERR_INVALID_ARG, "mixed_create: 1 to 8 codes");
+    if (max_batch < 1) return set_error(QLDPC_ERR_INVALID_ARG, "mixed_create: max_batch must be positive");
+    if (params->fmt != QLDPC_F32 || params->sched != QLDPC_FLOOD || params->prior_mode != QLDPC_PRIOR_PER_SHOT)
+        return set_error(QLDPC_ERR_UNSUPPORTED, "mixed_create: FP32 flooding with per-shot priors only");
+    if (params->max_iters < 1 || params->max_iters > 255 || !(params->alpha > 0.f && params->alpha <= 1.f))
+        return set_error(QLDPC_ERR_INVALID_ARG, "mixed_create: bad iterations or alpha");
+    for (int c = 0; c < ncodes; ++c) {
+        if (!codes[c]) return set_error(QLDPC_ERR_INVALID_ARG, "mixed_create: null code");
+        if (codes[c]->which != 0) return set_error(QLDPC_ERR_UNSUPPORTED, "mixed_create: H_Z patterns only");
+        if (codes[c]->device != codes[0]->device) return set_error(QLDPC_ERR_INVALID_ARG, "mixed_create: codes on different devices");
+    }
+    auto *x = new (std::nothrow) qldpc_mixed_s();
+    if (!x) return set_error(QLDPC_ERR_OUT_OF_MEMORY, "mixed_create: host allocation");
+    x->ncodes = ncodes;
+    x->max_batch = max_batch;
+    x->use_graph = use_graph ? 1 : 0;
+    x->device = codes[0]->device;
+    std::copy(codes, codes + ncodes, x->codes);
+    x->params = *params;
+    int cus = 256;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
+    x->waves = 4 * cus;   // two 61 KB waves fit per CU; two rounds of them by default
+    hipError_t e = hipSetDevice(x->device);
+    if (e == hipSuccess) e = hipMalloc(&x->scratch, sizeof(int32_t) * (2 * kMaxMixCodes + 1 + (size_t)max_batch));
+    if (e != hipSuccess) {
+        delete x;
+        return set_error(QLDPC_ERR_OUT_OF_MEMORY, "mixed_create: scratch allocation");
+    }
+    *out = x;
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_mixed_destroy(qldpc_mixed x) {
+    if (!x) return QLDPC_OK;
+    for (auto &kv : x->graphs) hipGraphExecDestroy(kv.second);
+    if (x->scratch) hipFree(x->scratch);
+    delete x;
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_mixed_decode(qldpc_mixed x, int32_t batch, const int32_t *shot_code, const int64_t *syn_off,
+                                const int64_t *err_off, const uint32_t *syn, const float *prior, uint32_t *err,
+                                uint8_t *conv, uint8_t *iters, void *stream) {
+    if (!x) return set_error(QLDPC_ERR_INVALID_ARG, "mixed_decode: null plan");
+    if (batch < 0 || batch > x->max_batch) return set_error(QLDPC_ERR_INVALID_ARG, "mixed_decode: batch out of range");
+    if (batch == 0) return QLDPC_OK;
+    if (!shot_code || !syn_off || !err_off || !syn || !prior || !err || !conv)
+        return set_error(QLDPC_ERR_INVALID_ARG, "mixed_decode: null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    if (!x->use_graph) return enqueue(x, batch, shot_code, syn_off, err_off, syn, prior, err, conv, iters, st, x->waves);
+    std::lock_guard<std::mutex> g(x->mu);
+    auto key = std::make_tuple(batch, (const void *)shot_code, (const void *)syn_off, (const void *)err_off,
+                               (const void *)syn, (const void *)prior, (const void *)err, (const void *)conv,
+                               (const void *)iters, (const void *)nullptr, (void *)st, x->waves);
+    auto it = x->graphs.find(key);
+    hipGraphExec_t ex = nullptr;
+    if (it == x->graphs.end()) {
+        if (x->graphs.size() >= 16) {
+            for (auto &kv : x->graphs) hipGraphExecDestroy(kv.second);
+            x->graphs.clear();
+        }
+        // capture on a private stream so the caller's stream is never in capture mode
+        hipStream_t cs = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_error(e, "mixed_decode: capture stream");
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            hipStreamDestroy(cs);
+            return hip_error(e, "mixed_decode: begin capture");
+        }
+        qldpc_status s2 = enqueue(x, batch, shot_code, syn_off, err_off, syn, prior, err, conv, iters, cs, x->waves);
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(cs, &gr);
+        hipStreamDestroy(cs);
+        if (s2 != QLDPC_OK) {
+            if (gr) hipGraphDestroy(gr);
+            return s2;
+        }
+        if (e != hipSuccess) return hip_error(e, "mixed_decode: end capture");
+        e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        hipGraphDestroy(gr);
+        if (e != hipSuccess) return hip_error(e, "mixed_decode: instantiate");
+        x->graphs[key] = ex;
+    } else {
+        ex = it->second;
+    }
+    hipError_t e = hipGraphLaunch(ex, st);
+    if (e != hipSuccess) return hip_error(e, "mixed_decode: graph launch");
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_mixed_autotune(qldpc_mixed x, int32_t batch, const int32_t *shot_code, const int64_t *syn_off,
+                                  const int64_t *err_off, const uint32_t *syn, const float *prior, uint32_t *err,
+                                  uint8_t *conv, uint8_t *iters, void *stream, int32_t *best_waves) {
+    if (!x || batch <= 0 || batch > x->max_batch || !best_waves)
+        return set_error(QLDPC_ERR_INVALID_ARG, "mixed_autotune: bad arguments");
+    if (!shot_code || !syn_off || !err_off || !syn || !prior || !err || !conv)
+        return set_error(QLDPC_ERR_INVALID_ARG, "mixed_autotune: null buffer");
+    int cus = 256;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return set_error(QLDPC_ERR_DEVICE, "mixed_autotune: event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return set_error(QLDPC_ERR_DEVICE, "mixed_autotune: event");
+    }
+    float best = 1e30f;
+    int bw = x->waves;
+    qldpc_status rc = QLDPC_OK;
+    for (int mult : {2, 4, 8, 16}) {
+        const int w = mult * cus;
+        rc = enqueue(x, batch, shot_code, syn_off, err_off, syn, prior, err, conv, iters, st, w);
+        if (rc != QLDPC_OK) break;
+        hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && rc == QLDPC_OK; ++r)
+            rc = enqueue(x, batch, shot_code, syn_off, err_off, syn, prior, err, conv, iters, st, w);
+        hipEventRecord(e1, st);
+        if (rc != QLDPC_OK) break;
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            bw = w;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != QLDPC_OK) return rc;
+    std::lock_guard<std::mutex> g(x->mu);
+    x->waves = bw;
+    *best_waves = bw;
+    return QLDPC_OK;
+}
+
+}  // extern "C"
