@@ -74,6 +74,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--latency-reqs", type=int, default=20000, help="requests per noise rate (0 = skip)")
+    ap.add_argument("--mixed-shots", type=int, default=262144, help="mixed-code batch size (0 = skip)")
     ap.add_argument("--seed", type=int, default=20250807)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run one plain device copy of MIB MiB (a known-size "
@@ -183,6 +184,43 @@ def main():
                 edge_model_GBps=float(sum(i * edge_model_bytes(E, bpm) + B * io_bytes for i in it_)
                                       / (k_.mean(axis=0).sum() * 1e-3) / 1e9))
 
+    # ---------------- mixed codes in one persistent launch ---------------------
+    mixed = None
+    if args.mixed_shots > 0:
+        from workload.mixed import MixedBatch
+        codes = [lp.lp_code(Lm) for Lm in (16, 32, 64, 128)]
+        decs = [Decoder(cc.hz, device=0) for cc in codes]
+        t0m = time.time()
+        mb = MixedBatch(codes, args.seed + 99, args.mixed_shots)
+        gen_m = time.time() - t0m
+        prm = decs[0].params(max_iters=32)
+        plan = abi.qldpc_mixed_create([d.handle for d in decs], prm, mb.B, True)
+        try:
+            dv = [torch.from_numpy(x).to(dev) for x in (mb.cid.astype(np.int32), mb.syn_off, mb.err_off,
+                                                          mb.syn.view(np.int32), mb.gamma)]
+            err_m = torch.empty(mb.err_words, dtype=torch.int32, device=dev)
+            conv_m = torch.empty(mb.B, dtype=torch.uint8, device=dev)
+            it_m = torch.empty(mb.B, dtype=torch.uint8, device=dev)
+            waves = abi.qldpc_mixed_autotune(plan, mb.B, *dv, err_m, conv_m, it_m)
+            abi.qldpc_mixed_decode(plan, mb.B, *dv, err_m, conv_m, it_m)     # capture + warm-up
+            torch.cuda.synchronize()
+            reps = max(3, args.steps // 4)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                abi.qldpc_mixed_decode(plan, mb.B, *dv, err_m, conv_m, it_m)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            itv = it_m.cpu().numpy().astype(np.int64)
+            mixed = dict(value=mb.B / (ms * 1e-3), unit="syndromes/s", ms_per_launch=ms, shots=mb.B,
+                         persistent_waves=waves, proportions=[float(x) for x in mb.prop],
+                         codes="L in {16,32,64,128}, per-shot p ~ U[0.01,0.08], FP32 flooding, <=32 iterations, "
+                               "hipGraph replay", mean_iters=float(itv.mean()),
+                         converged=float(conv_m.float().mean().item()), input_generation_s=gen_m)
+        finally:
+            abi.qldpc_mixed_destroy(plan)
+
     # ---------------- latency: one syndrome per request, host to host ---------
     latency = None
     if args.latency_reqs > 0:
@@ -266,6 +304,7 @@ def main():
                      "both passes) + 398 B I/O per shot; the kernel keeps these bytes in LDS",
         },
         "latency_us": latency,
+        "mixed_batch": mixed,
         "cpu_baseline": cpu,
         "ler": ler,
         "variants": variants,

@@ -301,6 +301,88 @@ qldpc_status qldpc_nbp_decode(qldpc_code code, int32_t batch, int32_t T, const f
                               const float *priors, uint32_t *errors, uint8_t *converged,
                               uint8_t *iters_used, uint8_t *used_fallback, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of decode requests (several asynchronous     */
+/* decoders overlapping copies and kernels, Table 1 and Section 3)           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct qldpc_server_s *qldpc_server;
+
+typedef struct {
+    const qldpc_code *codes;          /* 1..8 codes served (H_Z pattern)            */
+    int32_t ncodes;
+    const float *const *nms_weights;  /* per code: device [nms_T][nnz] neural weights
+                                         or NULL (plain min-sum only); the array may
+                                         itself be NULL                               */
+    int32_t nms_T;                    /* neural iterations before the fallback      */
+    qldpc_decode_params params;       /* plain min-sum and fallback: FP32 flooding,
+                                         per-shot priors                             */
+    size_t hbm_budget;                /* device bytes for in-flight work, 0 = no cap;
+                                         slots = min(max_inflight, budget / slot)    */
+    int32_t max_inflight;             /* micro-batches on the device at once        */
+    int32_t max_batch_shots;          /* shots per micro-batch (largest request)    */
+    int32_t queue_capacity;           /* queued requests before submit refuses      */
+} qldpc_server_config;
+
+typedef struct {
+    uint64_t req_id;
+    int32_t code_id, decoder, nshots, status;
+    int64_t t_submit_ns, t_done_ns;   /* steady clock                               */
+} qldpc_completion;
+
+/* Starts the server: allocates every slot (device buffers, pinned staging,
+ * stream, mixed-code plan) up front and a scheduler thread.  CAPACITY if the
+ * HBM budget is below one slot. */
+qldpc_status qldpc_server_create(const qldpc_server_config *cfg, qldpc_server *out);
+
+/* Slot count, device bytes per slot, queued requests, shots on the device. */
+qldpc_status qldpc_server_info(qldpc_server srv, int32_t *slots, size_t *slot_bytes, int32_t *pending,
+                               int64_t *inflight_shots);
+
+/* Queues a request of nshots syndromes of code code_id (host uint32
+ * [nshots][ceil(m/32)]) with per-shot priors (host float [nshots]);
+ * decoder 0 = plain min-sum, 1 = neural min-sum with fallback.  Results go
+ * to the caller's host buffers (errors [nshots][ceil(n/32)], converged and
+ * iters [nshots]; any may be NULL), which must stay valid until the
+ * request's completion is polled.  CAPACITY when the queue is full (the
+ * request is not queued). */
+qldpc_status qldpc_server_submit(qldpc_server srv, int32_t code_id, int32_t decoder, int32_t nshots,
+                                 const uint32_t *host_syndromes, const float *host_priors,
+                                 uint32_t *host_errors, uint8_t *host_converged, uint8_t *host_iters,
+                                 uint64_t req_id);
+
+/* Moves up to `max` completions (oldest first) to `out`; NOT_READY when none. */
+qldpc_status qldpc_server_poll(qldpc_server srv, qldpc_completion *out, int32_t max, int32_t *n_out);
+
+/* Stops admitting, waits for the micro-batches on the device, frees all. */
+qldpc_status qldpc_server_destroy(qldpc_server srv);
+
+typedef struct {
+    double rate_shots_per_s;          /* offered load                               */
+    double duration_s;                /* length of the arrival process              */
+    uint64_t seed;
+    double p_single;                  /* P(request = 1 shot), else 64 shots         */
+    double p_neural;                  /* P(neural decoder) where weights exist      */
+    int32_t ncodes;                   /* = the server's code count                  */
+    const uint32_t *const *pool_syn;  /* per code: host [pool][ceil(m/32)]          */
+    const float *const *pool_prior;   /* per code: host [pool]                      */
+    const int32_t *pool_size;         /* per code, >= 64                            */
+} qldpc_loadgen_config;
+
+typedef struct {
+    int64_t requests, shots, rejected;
+    double wall_s, offered_s;
+    double p50_us, p99_us, p999_us, mean_us, max_us;  /* from scheduled arrival      */
+    double shots_per_s;
+} qldpc_loadgen_result;
+
+/* Drives an idle server with an open-loop Poisson stream of requests drawn
+ * from host pools (uniform code, size 1 or 64, plain or neural) and
+ * measures each latency from its scheduled arrival to its completion.
+ * lat_us (nullable) receives up to lat_cap per-request latencies. */
+qldpc_status qldpc_server_loadgen(qldpc_server srv, const qldpc_loadgen_config *cfg,
+                                  qldpc_loadgen_result *result, double *lat_us, int64_t lat_cap);
+
 /* Host helper: int8 Q4 prior clamp(round-half-away-from-zero(16 * llr),
  * -127, 127) for `count` values (host arrays). */
 qldpc_status qldpc_quantize_prior(const float *llr, int8_t *out, int64_t count);

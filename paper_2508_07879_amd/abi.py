@@ -49,6 +49,32 @@ class qldpc_decode_params(C.Structure):
                 ("prior_mode", C.c_int32), ("layout", C.c_int32), ("waves_per_shot", C.c_int32)]
 
 
+class qldpc_server_config(C.Structure):
+    _fields_ = [("codes", C.POINTER(C.c_void_p)), ("ncodes", C.c_int32),
+                ("nms_weights", C.POINTER(C.c_void_p)), ("nms_T", C.c_int32),
+                ("params", qldpc_decode_params), ("hbm_budget", C.c_size_t),
+                ("max_inflight", C.c_int32), ("max_batch_shots", C.c_int32), ("queue_capacity", C.c_int32)]
+
+
+class qldpc_completion(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("code_id", C.c_int32), ("decoder", C.c_int32), ("nshots", C.c_int32),
+                ("status", C.c_int32), ("t_submit_ns", C.c_int64), ("t_done_ns", C.c_int64)]
+
+
+class qldpc_loadgen_config(C.Structure):
+    _fields_ = [("rate_shots_per_s", C.c_double), ("duration_s", C.c_double), ("seed", C.c_uint64),
+                ("p_single", C.c_double), ("p_neural", C.c_double), ("ncodes", C.c_int32),
+                ("pool_syn", C.POINTER(C.c_void_p)), ("pool_prior", C.POINTER(C.c_void_p)),
+                ("pool_size", C.POINTER(C.c_int32))]
+
+
+class qldpc_loadgen_result(C.Structure):
+    _fields_ = [("requests", C.c_int64), ("shots", C.c_int64), ("rejected", C.c_int64),
+                ("wall_s", C.c_double), ("offered_s", C.c_double), ("p50_us", C.c_double),
+                ("p99_us", C.c_double), ("p999_us", C.c_double), ("mean_us", C.c_double),
+                ("max_us", C.c_double), ("shots_per_s", C.c_double)]
+
+
 def _load():
     # torch loads its own HIP runtime under the unversioned file name; let it
     # initialise first so that libqldpc.so binds to that same runtime (same
@@ -84,6 +110,13 @@ def _load():
         "qldpc_mixed_destroy": ([vp], i32),
         "qldpc_mixed_decode": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "qldpc_mixed_autotune": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32)], i32),
+        "qldpc_server_create": ([C.POINTER(qldpc_server_config), C.POINTER(vp)], i32),
+        "qldpc_server_info": ([vp, vp, vp, vp, vp], i32),
+        "qldpc_server_submit": ([vp, i32, i32, i32, vp, vp, vp, vp, vp, C.c_uint64], i32),
+        "qldpc_server_poll": ([vp, vp, i32, C.POINTER(i32)], i32),
+        "qldpc_server_destroy": ([vp], i32),
+        "qldpc_server_loadgen": ([vp, C.POINTER(qldpc_loadgen_config), C.POINTER(qldpc_loadgen_result), vp,
+                                  i64], i32),
         "qldpc_nbp_workspace_bytes": ([vp, i32, i32, C.POINTER(C.c_size_t)], i32),
         "qldpc_nbp_forward": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], i32),
         "qldpc_nbp_backward": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], i32),
@@ -268,3 +301,72 @@ def qldpc_mixed_autotune(x, batch: int, shot_code, syn_off, err_off, syndromes, 
                                     _ptr(priors), _ptr(errors), _ptr(converged), _ptr(iters_used), _stream(stream),
                                     C.byref(w)))
     return int(w.value)
+
+
+def qldpc_server_create(handles, params: qldpc_decode_params, nms_weights=None, nms_T: int = 0,
+                        hbm_budget: int = 0, max_inflight: int = 4, max_batch_shots: int = 4096,
+                        queue_capacity: int = 65536):
+    """nms_weights: None or a list (one per code) of device tensors / None."""
+    cfg = qldpc_server_config()
+    codes = (C.c_void_p * len(handles))(*[h.value for h in handles])
+    cfg.codes = C.cast(codes, C.POINTER(C.c_void_p))
+    cfg.ncodes = len(handles)
+    keep = [codes]
+    if nms_weights is not None:
+        ws = (C.c_void_p * len(handles))(*[None if w is None else w.data_ptr() for w in nms_weights])
+        cfg.nms_weights = C.cast(ws, C.POINTER(C.c_void_p))
+        keep.append(ws)
+    cfg.nms_T = int(nms_T)
+    cfg.params = params
+    cfg.hbm_budget = int(hbm_budget)
+    cfg.max_inflight = int(max_inflight)
+    cfg.max_batch_shots = int(max_batch_shots)
+    cfg.queue_capacity = int(queue_capacity)
+    srv = C.c_void_p()
+    _check(lib.qldpc_server_create(C.byref(cfg), C.byref(srv)))
+    return srv
+
+
+def qldpc_server_info(srv):
+    a, b, c_, d = C.c_int32(), C.c_size_t(), C.c_int32(), C.c_int64()
+    _check(lib.qldpc_server_info(srv, C.byref(a), C.byref(b), C.byref(c_), C.byref(d)))
+    return int(a.value), int(b.value), int(c_.value), int(d.value)
+
+
+def qldpc_server_submit(srv, code_id: int, decoder: int, nshots: int, host_syn, host_prior, host_err=None,
+                        host_conv=None, host_iters=None, req_id: int = 0) -> None:
+    _check(lib.qldpc_server_submit(srv, int(code_id), int(decoder), int(nshots), _np(host_syn), _np(host_prior),
+                                   _np(host_err), _np(host_conv), _np(host_iters), C.c_uint64(req_id)))
+
+
+def qldpc_server_poll(srv, max_n: int = 1024):
+    buf = (qldpc_completion * max_n)()
+    n = C.c_int32()
+    st = lib.qldpc_server_poll(srv, buf, int(max_n), C.byref(n))
+    if st not in (QLDPC_OK, QLDPC_ERR_NOT_READY):
+        _check(st)
+    return [buf[i] for i in range(n.value)]
+
+
+def qldpc_server_destroy(srv) -> None:
+    _check(lib.qldpc_server_destroy(srv))
+
+
+def qldpc_server_loadgen(srv, rate: float, duration: float, pools_syn, pools_prior, seed: int = 1,
+                         p_single: float = 0.5, p_neural: float = 0.5, lat_cap: int = 0):
+    """pools_*: per code host numpy arrays ([pool, words] uint32, [pool] float32)."""
+    n = len(pools_syn)
+    cfg = qldpc_loadgen_config()
+    cfg.rate_shots_per_s, cfg.duration_s, cfg.seed = float(rate), float(duration), int(seed)
+    cfg.p_single, cfg.p_neural, cfg.ncodes = float(p_single), float(p_neural), n
+    ps = (C.c_void_p * n)(*[a.ctypes.data for a in pools_syn])
+    pp = (C.c_void_p * n)(*[a.ctypes.data for a in pools_prior])
+    sz = (C.c_int32 * n)(*[int(a.shape[0]) for a in pools_prior])
+    cfg.pool_syn = C.cast(ps, C.POINTER(C.c_void_p))
+    cfg.pool_prior = C.cast(pp, C.POINTER(C.c_void_p))
+    cfg.pool_size = C.cast(sz, C.POINTER(C.c_int32))
+    res = qldpc_loadgen_result()
+    lat = np.zeros(max(1, int(lat_cap)), np.float64)
+    _check(lib.qldpc_server_loadgen(srv, C.byref(cfg), C.byref(res), _np(lat), int(lat_cap)))
+    out = {f: getattr(res, f) for f, _ in qldpc_loadgen_result._fields_}
+    return out, lat[:min(int(lat_cap), out["requests"])]

@@ -33,12 +33,22 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+def _deps(src: str, seen=None) -> set:
+    """The file and every local header it includes, transitively."""
+    import re
+    seen = set() if seen is None else seen
+    if src in seen or not os.path.exists(src):
+        return seen
+    seen.add(src)
+    for inc in re.findall(r'^\s*#\s*include\s+"([^"]+)"', open(src).read(), flags=re.M):
+        _deps(os.path.normpath(os.path.join(os.path.dirname(src), inc)), seen)
+    return seen
+
+
 def _stale(src: str, obj: str) -> bool:
     if not os.path.exists(obj):
         return True
-    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
-    deps.append(os.path.join(ROOT, "include", "qldpc.h"))
-    return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
+    return max(os.path.getmtime(d) for d in _deps(src)) > os.path.getmtime(obj)
 
 
 def _compile(src: str, verbose: bool, incremental: bool = False) -> str:
