@@ -39,6 +39,28 @@
 
 namespace qldpc {
 
+// Scheduling knobs of the unrolled passes, per message format (measured on
+// MI355X at L = 64, 65536 shots):
+//  - sched group: a scheduling barrier after every G block rows (check pass)
+//    and every G column batches (variable pass) bounds how far the compiler
+//    hoists LDS loads, i.e. the registers a wave needs.  int8 kernels hold
+//    little LDS and gain occupancy from it (11.9 -> 22 M syndromes/s); the
+//    FP32 kernels are LDS-occupancy bound and lose ILP from it.  0 = none.
+//  - variable-pass batch: block columns whose messages are all loaded
+//    before any is overwritten (see the variable pass).
+//  - wave cap: the most waves per SIMD the register allocation targets.
+template <int FMT> struct Knobs;
+template <> struct Knobs<0> { static constexpr int sched_group = 0, vn_batch = 4, wave_cap = 1; };
+template <> struct Knobs<1> { static constexpr int sched_group = 1, vn_batch = 2, wave_cap = 4; };
+
+template <int FMT>
+__device__ __forceinline__ void sched_group_end(int idx) {
+    constexpr int g = Knobs<FMT>::sched_group;
+    if constexpr (g > 0) {
+        if ((idx + 1) % g == 0) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 template <class S, int L>
 struct Geo {
     static constexpr int SEG = L < 64 ? L : 64;      // lanes per shot
@@ -379,6 +401,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                             msg[(R * DC + j) * ROW + lane + 64 * h] = (msg_t)v[j];
                     }
                 }
+                sched_group_end<FMT>(R);
             }
             __builtin_amdgcn_wave_barrier();
         } else {
@@ -429,69 +452,92 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
         }
 
         // ---------------- variable nodes, a posteriori, decision -------------
-        static_for<0, NB>([&](auto Cc) {
-            constexpr int C = decltype(Cc)::value;
-            constexpr int d = S::T.col_deg[C];
-            uint64_t mask[H];
+        // Block columns are processed Knobs::vn_batch at a time: every message
+        // of the batch is loaded before any is overwritten, so the rotated
+        // loads of a batch overlap instead of each column waiting for the
+        // previous column's stores (the compiler cannot prove that rotated
+        // addresses of different columns never alias).
+        constexpr int VB = Knobs<FMT>::vn_batch;
+        static_for<0, (NB + VB - 1) / VB>([&](auto Bc) {
+            constexpr int C0 = decltype(Bc)::value * VB;
+            constexpr int NC = (C0 + VB <= NB) ? VB : NB - C0;
+            acc_t rr[NC][H][kMaxDv];
+            int ii[NC][H][kMaxDv];
+            if constexpr (SCHED == 0) {
+                static_for<0, NC>([&](auto Kc) {
+                    constexpr int kc = decltype(Kc)::value;
+                    constexpr int C = C0 + kc;
 #pragma unroll
-            for (int h = 0; h < H; ++h) {
-                acc_t Q;
-                if constexpr (SCHED == 0) {
-                    acc_t r[d];
-                    int idx[d];
-                    static_for<0, d>([&](auto Ii) {
-                        constexpr int i = decltype(Ii)::value;
-                        constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
-                        idx[i] = slot * ROW + vn_at(h, (uint32_t)code->shift[slot]);
-                        r[i] = (acc_t)msg[idx[i]];
-                    });
-                    if constexpr (FMT == 0) {
-                        // prefix sums from gamma in increasing check order; the
-                        // excluded sum of edge i continues the prefix before i
-                        float pre[d + 1];
-                        pre[0] = gamma_of(C, h);
-#pragma unroll
-                        for (int i = 0; i < d; ++i) pre[i + 1] = pre[i] + r[i];
-#pragma unroll
-                        for (int i = 0; i < d; ++i) {
-                            float q = pre[i];
-#pragma unroll
-                            for (int j = i + 1; j < d; ++j) q = q + r[j];
-                            msg[idx[i]] = q;
-                        }
-                        Q = pre[d];
-                    } else {
-                        int sum = gamma_of(C, h);
-#pragma unroll
-                        for (int i = 0; i < d; ++i) sum += r[i];
-#pragma unroll
-                        for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
-                        Q = sum;
+                    for (int h = 0; h < H; ++h) {
+                        static_for<0, S::T.col_deg[C]>([&](auto Ii) {
+                            constexpr int i = decltype(Ii)::value;
+                            constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
+                            ii[kc][h][i] = slot * ROW + vn_at(h, (uint32_t)code->shift[slot]);
+                            rr[kc][h][i] = (acc_t)msg[ii[kc][h][i]];
+                        });
                     }
-                } else {
-                    Q = (acc_t)Qs[C * ROW + lane + 64 * h];
-                }
-                if constexpr (POST) Qr[C * H + h] = Q;
-                const bool e = Q < (acc_t)0;
-                eb[h] |= (uint64_t)e << C;
-                mask[h] = ballot(e);
+                });
             }
-            // syndrome accumulation in scalar registers
-            static_for<0, d>([&](auto Ii) {
-                constexpr int i = decltype(Ii)::value;
-                constexpr int R = S::T.col_R[C][i];
-                constexpr int slot = R * DC + S::T.col_j[C][i];
-                const uint32_t s = (uint32_t)code->shift[slot];
-                if constexpr (GRP) {
+            static_for<0, NC>([&](auto Kc) {
+                constexpr int kc = decltype(Kc)::value;
+                constexpr int C = C0 + kc;
+                constexpr int d = S::T.col_deg[C];
+                uint64_t mask[H];
 #pragma unroll
-                    for (int h = 0; h < H; ++h) acc[R][h] ^= seg_rotr<L>(mask[h], s, code->lowmask[slot]);
-                } else {
-                    uint64_t lo, hi;
-                    rotr128(mask[0], mask[H - 1], s, lo, hi);
-                    acc[R][0] ^= lo;
-                    acc[R][H - 1] ^= hi;
+                for (int h = 0; h < H; ++h) {
+                    acc_t Q;
+                    if constexpr (SCHED == 0) {
+                        const acc_t *r = rr[kc][h];
+                        const int *idx = ii[kc][h];
+                        if constexpr (FMT == 0) {
+                            // prefix sums from gamma in increasing check order; the
+                            // excluded sum of edge i continues the prefix before i
+                            float pre[d + 1];
+                            pre[0] = gamma_of(C, h);
+#pragma unroll
+                            for (int i = 0; i < d; ++i) pre[i + 1] = pre[i] + r[i];
+#pragma unroll
+                            for (int i = 0; i < d; ++i) {
+                                float q = pre[i];
+#pragma unroll
+                                for (int j = i + 1; j < d; ++j) q = q + r[j];
+                                msg[idx[i]] = q;
+                            }
+                            Q = pre[d];
+                        } else {
+                            int sum = gamma_of(C, h);
+#pragma unroll
+                            for (int i = 0; i < d; ++i) sum += r[i];
+#pragma unroll
+                            for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
+                            Q = sum;
+                        }
+                    } else {
+                        Q = (acc_t)Qs[C * ROW + lane + 64 * h];
+                    }
+                    if constexpr (POST) Qr[C * H + h] = Q;
+                    const bool e = Q < (acc_t)0;
+                    eb[h] |= (uint64_t)e << C;
+                    mask[h] = ballot(e);
                 }
+                // syndrome accumulation in scalar registers
+                static_for<0, d>([&](auto Ii) {
+                    constexpr int i = decltype(Ii)::value;
+                    constexpr int R = S::T.col_R[C][i];
+                    constexpr int slot = R * DC + S::T.col_j[C][i];
+                    const uint32_t s = (uint32_t)code->shift[slot];
+                    if constexpr (GRP) {
+#pragma unroll
+                        for (int h = 0; h < H; ++h) acc[R][h] ^= seg_rotr<L>(mask[h], s, code->lowmask[slot]);
+                    } else {
+                        uint64_t lo, hi;
+                        rotr128(mask[0], mask[H - 1], s, lo, hi);
+                        acc[R][0] ^= lo;
+                        acc[R][H - 1] ^= hi;
+                    }
+                });
             });
+            sched_group_end<FMT>(decltype(Bc)::value);
         });
 
         // ---------------- stopping rule, outputs ------------------------------
@@ -577,9 +623,22 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     }
 }
 
+// Waves per SIMD the register allocation must leave room for: as many as
+// the kernel's LDS footprint lets a compute unit hold (160 KB / 4 SIMDs),
+// capped per format so the scheduler keeps registers for latency hiding.
+template <class S, int L, int FMT, int SCHED>
+constexpr int wave_occupancy() {
+    constexpr size_t b = WaveLds<S, L, FMT, SCHED, 1>::bytes;
+    constexpr int per_cu = (int)((160 * 1024) / b);
+    constexpr int per_simd = per_cu / 4;
+    constexpr int cap = Knobs<FMT>::wave_cap;
+    return per_simd < 1 ? 1 : (per_simd > cap ? cap : per_simd);
+}
+
 // One wave per workgroup; grid = ceil(batch / shots-per-wave).
 template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED = false>
-__global__ __launch_bounds__(64) void k_wave(const DecodeArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<S, L, FMT, SCHED>())))
+void k_wave(const DecodeArgs a) {
     using G = Geo<S, L>;
     using Lay = WaveLds<S, L, FMT, SCHED, 1>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
