@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--cpu-shots", type=int, default=8192, help="oracle sample per noise rate")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--latency-reqs", type=int, default=20000, help="requests per noise rate (0 = skip)")
+    ap.add_argument("--latency-reqs", type=int, default=100000, help="requests per noise rate (0 = skip)")
     ap.add_argument("--mixed-shots", type=int, default=262144, help="mixed-code batch size (0 = skip)")
     ap.add_argument("--seed", type=int, default=20250807)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -168,6 +168,7 @@ def main():
         fails = gf2.logical_failures(lam, bb["batch"].e, e_hat, conv)
         k = int(fails.sum())
         lo, hi = gf2.wilson(k, B)
+        bb["iters_host"] = it
         ler[str(bb["p"])] = dict(ler=k / B, ci95=[lo, hi], converged=float(conv.mean()),
                                  mean_iters=float(it.mean()), p99_iters=float(np.percentile(it, 99)))
 
@@ -226,27 +227,42 @@ def main():
     if args.latency_reqs > 0:
         latency = {}
         pool = 4096
-        for mode_name, early, iters in (("early_stop", 1, 32), ("all_32_iterations", 0, 32)):
-            prm = dec.params(fmt=abi.QLDPC_F32, sched=abi.QLDPC_FLOOD, max_iters=iters, early_stop=bool(early))
-            sess = abi.qldpc_session_create(dec.handle, prm, 1, abi.QLDPC_IO_MAPPED)
+
+        def lat_stats(lat):
+            return dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
+                        p999=float(np.percentile(lat, 99.9)), mean=float(lat.mean()), requests=int(lat.size))
+
+        for mode_name, io, early in (("early_stop", abi.QLDPC_IO_RESIDENT, True),
+                                     ("all_32_iterations", abi.QLDPC_IO_RESIDENT, False),
+                                     ("all_32_iterations_launch_per_request", abi.QLDPC_IO_MAPPED, False)):
+            prm = dec.params(fmt=abi.QLDPC_F32, sched=abi.QLDPC_FLOOD, max_iters=32, early_stop=early,
+                             layout=abi.QLDPC_LAYOUT_BLOCK)
+            sess = abi.qldpc_session_create(dec.handle, prm, 1, io)
             try:
                 per_p = {}
                 for bb in batches:
                     syn_h = np.ascontiguousarray(bits.pack_bits(bb["batch"].s[:pool]))
                     pr_h = np.ascontiguousarray(bb["batch"].gamma[:pool])
-                    abi.qldpc_session_latency(sess, 200, 1, pool, syn_h, pr_h)      # warm-up
+                    abi.qldpc_session_latency(sess, 500, 1, pool, syn_h, pr_h)      # warm-up
                     lat = abi.qldpc_session_latency(sess, args.latency_reqs, 1, pool, syn_h, pr_h)
-                    per_p[str(bb["p"])] = dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
-                                               p999=float(np.percentile(lat, 99.9)), mean=float(lat.mean()),
-                                               requests=int(lat.size))
-                    if mode_name == "all_32_iterations":
+                    st = lat_stats(lat)
+                    if early:
+                        # requests cycle through the pool; the share that needed all 32 iterations
+                        it = bb["iters_host"][:pool].astype(np.int64)
+                        st["share_all_32_iterations"] = float(np.mean(it[np.arange(lat.size) % pool] >= 32))
+                    per_p[str(bb["p"])] = st
+                    print(json.dumps({"latency": mode_name, "p": bb["p"], **st}), file=sys.stderr, flush=True)
+                    if not early:
                         break
                 latency[mode_name] = per_p
             finally:
                 abi.qldpc_session_destroy(sess)
-        latency["definition"] = ("one syndrome per request, from host memory to the decision in host "
-                                 "memory (fine-grained pinned buffers read and written by the kernel), "
-                                 "workgroup-per-shot layout, FP32 flooding, steady-clock per request")
+        latency["definition"] = ("one syndrome per request, from host memory to the decision in host memory, "
+                                 "steady-clock per request; FP32 flooding, workgroup-per-shot layout (16 waves). "
+                                 "early_stop and all_32_iterations: resident decoder woken through a doorbell in "
+                                 "fine-grained host memory (no launch, no stream synchronisation per request); "
+                                 "all_32_iterations_launch_per_request: one kernel launch and stream "
+                                 "synchronisation per request, same buffers")
 
     # ---------------- CPU oracle on a bounded sample ---------------------------
     cpu = None

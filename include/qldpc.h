@@ -195,8 +195,26 @@ typedef enum {
     QLDPC_IO_COPY = 0,   /* pinned staging + copy-in, decode, copy-out on a
                             private stream, captured once as a hipGraph per
                             batch size                                          */
-    QLDPC_IO_MAPPED = 1  /* the kernel reads syndromes and writes results in
+    QLDPC_IO_MAPPED = 1, /* the kernel reads syndromes and writes results in
                             pinned host memory directly (no copy commands)     */
+    QLDPC_IO_RESIDENT = 2 /* as MAPPED, with the decoder kept resident on the
+                            GPU between requests: one workgroup per shot slot
+                            polls a doorbell page in host memory, so a request
+                            costs no launch and no stream synchronisation.
+                            Flooding with L >= 64 only (the workgroup layout;
+                            waves_per_shot 8 or 16, default 16); max_batch <=
+                            64; no posteriors.  The grid occupies max_batch
+                            compute units while it waits; it leaves after
+                            200 ms without a request (the next request
+                            relaunches it) or when the session is destroyed.
+                            A device-wide synchronisation on the same device
+                            (hipDeviceSynchronize, torch.cuda.synchronize)
+                            therefore waits up to that idle time.  A request
+                            with no answer after 10 s fails with
+                            QLDPC_ERR_DEVICE; so does qldpc_session_destroy
+                            if the grid has not left 10 s after it was asked
+                            to (the session is then leaked, not freed under
+                            a running kernel).                                  */
 } qldpc_io_mode;
 
 /* A session owns device buffers and pinned host staging for up to

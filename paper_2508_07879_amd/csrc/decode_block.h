@@ -30,11 +30,14 @@ struct BlockLds {
     static constexpr size_t msg_bytes = (size_t)S::SLOTS * L * sizeof(msg_t);
     static constexpr size_t e_off = (msg_bytes + 15) & ~size_t(15);   // uint64 [NB][PPL]
     static constexpr size_t f_off = e_off + (size_t)S::NB * PPL * 8;  // uint32 flags[2]
-    static constexpr size_t bytes = f_off + 16;
+    static constexpr size_t s_off = f_off + 16;                          // uint32 syndrome words
+    static constexpr size_t bytes = s_off + (((size_t)S::MB * L + 31) / 32) * 4;
 };
 
+// Decodes shot `shot` with the whole workgroup; `lds` holds
+// BlockLds<S, L, FMT, NW>::bytes.  Every thread of the workgroup must call it.
 template <class S, int L, int FMT, int NW, bool PER_BIT, bool POST>
-__global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
+__device__ __forceinline__ void block_decode(const DecodeArgs &a, const long shot, unsigned char *lds) {
     using namespace wave;
     static_assert(L == 64 || L == 128, "block layout needs L >= 64");
     using Lay = BlockLds<S, L, FMT, NW>;
@@ -47,28 +50,18 @@ __global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
     constexpr int CN_ITEMS = MB * PPL, VN_ITEMS = NB * PPL;
     constexpr int VN_PER_WAVE = (VN_ITEMS + NW - 1) / NW;
 
-    __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
     msg_t *msg = reinterpret_cast<msg_t *>(lds);
     uint64_t *emask = reinterpret_cast<uint64_t *>(lds + Lay::e_off);
     uint32_t *flag = reinterpret_cast<uint32_t *>(lds + Lay::f_off);
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long shot = blockIdx.x;
-    const DevCode *__restrict__ code = a.code;
-    if (a.only && a.only[shot] == 0) return;   // uniform over the workgroup
+    const CodePtr code = const_code(a.code);
+    uint32_t *synw = reinterpret_cast<uint32_t *>(lds + Lay::s_off);
 
-    // syndrome bits of the checks this lane owns in each block row
-    uint32_t sb[PPL];
-#pragma unroll
-    for (int h = 0; h < PPL; ++h) {
-        sb[h] = 0;
-#pragma unroll
-        for (int R = 0; R < MB; ++R) {
-            const int m = R * L + lane + 64 * h;
-            sb[h] |= ((a.syn[shot * SW + (m >> 5)] >> (m & 31)) & 1u) << R;
-        }
-    }
+    // the shot's syndrome words are read from memory once per workgroup (the
+    // latency path reads them across the bus) and shared through LDS
+    for (int w = threadIdx.x; w < SW; w += 64 * NW) synw[w] = a.syn[shot * SW + w];
     // priors of this wave's variable items (canonicalised: no message is -0.0)
     acc_t gam[PER_BIT ? VN_PER_WAVE : 1];
     if constexpr (!PER_BIT) {
@@ -106,6 +99,18 @@ __global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
     }
     acc_t Qr[POST ? VN_PER_WAVE : 1];
     __syncthreads();
+
+    // syndrome bits of the checks this lane owns in each block row
+    uint32_t sb[PPL];
+#pragma unroll
+    for (int h = 0; h < PPL; ++h) {
+        sb[h] = 0;
+#pragma unroll
+        for (int R = 0; R < MB; ++R) {
+            const int m = R * L + lane + 64 * h;
+            sb[h] |= ((synw[m >> 5] >> (m & 31)) & 1u) << R;
+        }
+    }
 
     auto emit = [&](int k, bool conv) {
         // e words straight from the ballots; conv / iters by thread 0
@@ -187,7 +192,7 @@ __global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
         });
         if (k > 1 && a.early_stop) test_rows(k & 1);
         __syncthreads();
-        if (k > 1 && a.early_stop && flag[k & 1] == 0) {
+        if (k > 1 && a.early_stop && __builtin_amdgcn_readfirstlane(flag[k & 1]) == 0) {   // uniform
             emit(k - 1, true);
             return;
         }
@@ -239,7 +244,15 @@ __global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
     --k;
     test_rows((k + 1) & 1);
     __syncthreads();
-    emit(k, flag[(k + 1) & 1] == 0);
+    emit(k, __builtin_amdgcn_readfirstlane(flag[(k + 1) & 1]) == 0);
+}
+
+template <class S, int L, int FMT, int NW, bool PER_BIT, bool POST>
+__global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[BlockLds<S, L, FMT, NW>::bytes];
+    const long shot = blockIdx.x;
+    if (a.only && a.only[shot] == 0) return;   // uniform over the workgroup
+    block_decode<S, L, FMT, NW, PER_BIT, POST>(a, shot, lds);
 }
 
 template <class S, int L, int FMT, int NW, bool PB, bool PO>

@@ -9,6 +9,8 @@ hipError_t launch_wave_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wave_L128(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_block_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_block_L128(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_resident_L64(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
+hipError_t launch_resident_L128(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
 
 hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t stream) {
     if (k.layout == 1) {
@@ -24,6 +26,13 @@ hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t st
         if (k.L == 64) return launch_block_L64(k, a, stream);
         if (k.L == 128) return launch_block_L128(k, a, stream);
     }
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_resident_decode(const LaunchKey &k, const ResidentArgs &r, int grid, hipStream_t stream) {
+    if (k.layout != 2) return hipErrorNotSupported;
+    if (k.L == 64) return launch_resident_L64(k, r, grid, stream);
+    if (k.L == 128) return launch_resident_L128(k, r, grid, stream);
     return hipErrorNotSupported;
 }
 

@@ -13,6 +13,17 @@ struct DevCode {
     uint64_t lowmask[kMaxSlots];  // L < 64: per-segment mask of the low L - shift bits
 };
 
+// A DevCode seen through the constant address space.  No kernel writes the
+// table; reading it this way makes the compiler fetch shifts with scalar
+// loads, so that the rotations built from them run once per wave on the
+// scalar unit.  The latency kernel, whose few waves per shot spend their
+// time in those rotations, reads it so; the throughput kernels do not: in
+// their hot loops the extra scalar loads cost more than the vector shifts
+// they replace.
+typedef const __attribute__((address_space(4))) DevCode *CodePtr;
+
+__device__ __forceinline__ CodePtr const_code(const DevCode *p) { return (CodePtr)p; }
+
 // Arguments shared by every decode kernel.
 struct DecodeArgs {
     const DevCode *code;
@@ -32,6 +43,31 @@ struct DecodeArgs {
     const float *weights;   // neural decode: [max_iters][nnz] per-edge scales
 };
 
+// Doorbell page of a resident decoder, in mapped (fine-grained) host memory.
+// The host writes `batch`, then `req_seq`; workgroup w of the resident grid
+// answers by writing the served sequence number to done_seq[w] after its
+// results are visible to the host.  `stop` asks the kernel to exit.
+constexpr int kMaxResident = 64;   // shots per request of a resident session
+
+struct ResidentRing {
+    uint64_t req_seq;
+    int32_t batch;
+    int32_t stop;
+    uint64_t pad[14];                  // done_seq starts on its own 128-byte line
+    uint64_t done_seq[kMaxResident];
+};
+
+// Arguments of the resident decoder: `a` points its syndrome, prior and result
+// buffers at mapped host staging; `cmd` is a device-memory mailbox
+// [seq, batch] through which workgroup 0 relays requests to the others.
+struct ResidentArgs {
+    DecodeArgs a;
+    ResidentRing *ring;
+    uint64_t *cmd;
+    uint64_t start_seq;    // last sequence number already served
+    uint64_t idle_ticks;   // wall-clock ticks without a request before exiting
+};
+
 struct LaunchKey {
     int which;      // 0 = H_Z pattern, 1 = H_X pattern
     int L;          // 16, 32, 64, 128
@@ -45,5 +81,7 @@ struct LaunchKey {
 
 // Returns hipErrorNotSupported when no kernel exists for the key.
 hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t stream);
+// Launches the resident decoder (workgroup layout only) with `grid` shot slots.
+hipError_t launch_resident_decode(const LaunchKey &k, const ResidentArgs &r, int grid, hipStream_t stream);
 
 }  // namespace qldpc

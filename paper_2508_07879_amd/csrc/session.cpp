@@ -6,13 +6,18 @@
 // captured once per batch size replays copy-in -> decode -> copy-out on the
 // session's stream.  QLDPC_IO_MAPPED: the decoder reads the pinned staging
 // and writes its results there directly (the GPU reaches host memory over
-// the bus), so a request is one kernel launch.
+// the bus), so a request is one kernel launch.  QLDPC_IO_RESIDENT: as MAPPED,
+// but the decoder stays resident between requests and is woken through a
+// doorbell page in host memory, so a request is a few host stores and a spin
+// on the answer: no launch, no stream synchronisation.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <map>
 #include <new>
+#include <thread>
 
 #include "internal.h"
 
@@ -42,11 +47,45 @@ struct qldpc_session_s {
     uint32_t *m_err = nullptr;
     uint8_t *m_conv = nullptr, *m_iters = nullptr;
     std::map<int32_t, hipGraphExec_t> graphs;
+    // RESIDENT mode
+    ResidentRing *ring = nullptr;     // doorbell page, host address
+    uint64_t *d_cmd = nullptr;        // device mailbox of the resident grid
+    hipEvent_t ev_exit = nullptr;     // recorded after each launch of the grid
+    LaunchKey rkey{};
+    ResidentArgs rargs{};
+    uint64_t seq = 0;                 // sequence number of the last request
+    bool running = false;             // a grid was launched and not seen to exit
+    std::chrono::steady_clock::time_point last_answer{};
 };
 
 namespace {
 
+// A resident grid leaves after this long without a request; the next request
+// then relaunches it.
+constexpr double kResidentIdleMs = 200.0;
+// A request that has no answer after this long fails with QLDPC_ERR_DEVICE.
+constexpr double kResidentTimeoutMs = 10000.0;
+
+// Asks a resident grid to leave and waits (bounded) until it has; false if
+// it is still running after kResidentTimeoutMs.
+bool resident_stop(qldpc_session s) {
+    if (!s->ring) return true;
+    __atomic_store_n(&s->ring->stop, 1, __ATOMIC_SEQ_CST);
+    const auto t0 = std::chrono::steady_clock::now();
+    while (s->stream && hipStreamQuery(s->stream) == hipErrorNotReady) {
+        if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() >
+            kResidentTimeoutMs)
+            return false;
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+    }
+    s->running = false;
+    return true;
+}
+
 void release(qldpc_session s) {
+    if (s->ring) hipHostFree(s->ring);
+    if (s->ev_exit) hipEventDestroy(s->ev_exit);
+    if (s->d_cmd) hipFree(s->d_cmd);
     for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
     if (s->d_syn) hipFree(s->d_syn);
     if (s->d_prior) hipFree(s->d_prior);
@@ -122,9 +161,73 @@ qldpc_status graph_for(qldpc_session s, int32_t batch, hipGraphExec_t *out) {
     return QLDPC_OK;
 }
 
+// Launches the resident grid, which then serves every request numbered after
+// `served`.
+qldpc_status resident_start(qldpc_session s, uint64_t served) {
+    ResidentArgs r = s->rargs;
+    r.start_seq = served;
+    hipError_t e = launch_resident_decode(s->rkey, r, s->max_batch, s->stream);
+    if (e == hipErrorNotSupported) return set_error(QLDPC_ERR_UNSUPPORTED, "session: no resident kernel for these parameters");
+    if (e != hipSuccess) return hip_error(e, "session: resident launch");
+    e = hipEventRecord(s->ev_exit, s->stream);
+    if (e != hipSuccess) return hip_error(e, "session: record");
+    s->running = true;
+    return QLDPC_OK;
+}
+
+// Whether the last launched grid is still on the GPU.
+qldpc_status resident_alive(qldpc_session s, bool *alive) {
+    *alive = false;
+    if (!s->running) return QLDPC_OK;
+    const hipError_t q = hipEventQuery(s->ev_exit);
+    if (q == hipErrorNotReady) {
+        *alive = true;
+        return QLDPC_OK;
+    }
+    s->running = false;
+    if (q != hipSuccess) return hip_error(q, "session: resident grid");
+    return QLDPC_OK;
+}
+
+qldpc_status run_resident(qldpc_session s, int32_t batch) {
+    using clk = std::chrono::steady_clock;
+    // A grid idle for about kResidentIdleMs may have left; ask the runtime only then.
+    const double since = std::chrono::duration<double, std::milli>(clk::now() - s->last_answer).count();
+    if (!s->running || since > 0.5 * kResidentIdleMs) {
+        bool alive = false;
+        qldpc_status st = resident_alive(s, &alive);
+        if (st == QLDPC_OK && !alive) st = resident_start(s, s->seq);
+        if (st != QLDPC_OK) return st;
+    }
+    const uint64_t seq = s->seq + 1;
+    std::atomic_thread_fence(std::memory_order_seq_cst);   // staged inputs before the doorbell
+    __atomic_store_n(&s->ring->batch, batch, __ATOMIC_RELAXED);
+    __atomic_store_n(&s->ring->req_seq, seq, __ATOMIC_RELEASE);
+    s->seq = seq;
+    const auto t0 = clk::now();
+    for (uint32_t spin = 1;; ++spin) {
+        int32_t w = 0;
+        while (w < batch && __atomic_load_n(&s->ring->done_seq[w], __ATOMIC_ACQUIRE) == seq) ++w;
+        if (w == batch) break;
+        if ((spin & 4095) == 0) {
+            // the grid may have timed out just before the doorbell rang
+            bool alive = false;
+            qldpc_status st = resident_alive(s, &alive);
+            if (st == QLDPC_OK && !alive) st = resident_start(s, seq - 1);
+            if (st != QLDPC_OK) return st;
+            if (std::chrono::duration<double, std::milli>(clk::now() - t0).count() > kResidentTimeoutMs)
+                return set_error(QLDPC_ERR_DEVICE, "session: the resident decoder did not answer");
+        }
+        __builtin_ia32_pause();
+    }
+    s->last_answer = clk::now();
+    return QLDPC_OK;
+}
+
 // Decode from the staging buffers, synchronously.
 qldpc_status run_staged(qldpc_session s, int32_t batch) {
     hipError_t e;
+    if (s->io_mode == QLDPC_IO_RESIDENT) return run_resident(s, batch);
     if (s->io_mode == QLDPC_IO_MAPPED) {
         qldpc_status st = enqueue(s, batch);
         if (st != QLDPC_OK) return st;
@@ -148,12 +251,18 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
                                   int32_t io_mode, qldpc_session *out) {
     if (!code || !params || !out) return set_error(QLDPC_ERR_INVALID_ARG, "session_create: null argument");
     if (max_batch <= 0) return set_error(QLDPC_ERR_INVALID_ARG, "session_create: max_batch must be positive");
-    if (io_mode != QLDPC_IO_COPY && io_mode != QLDPC_IO_MAPPED)
+    if (io_mode != QLDPC_IO_COPY && io_mode != QLDPC_IO_MAPPED && io_mode != QLDPC_IO_RESIDENT)
         return set_error(QLDPC_ERR_INVALID_ARG, "session_create: bad io mode");
+    const bool resident = io_mode == QLDPC_IO_RESIDENT;
+    if (resident && max_batch > kMaxResident)
+        return set_error(QLDPC_ERR_INVALID_ARG, "session_create: a resident session takes at most 64 shots");
+    qldpc_decode_params prm = *params;
+    if (resident) prm.layout = QLDPC_LAYOUT_BLOCK;   // the resident grid is workgroup-per-shot
     LaunchKey k{};
     DecodeArgs a{};
-    qldpc_status st = prepare_decode(code, params, max_batch, &k, &a);   // validates params
+    qldpc_status st = prepare_decode(code, &prm, max_batch, &k, &a);   // validates params
     if (st != QLDPC_OK) return st;
+    params = &prm;
     auto *s = new (std::nothrow) qldpc_session_s();
     if (!s) return set_error(QLDPC_ERR_OUT_OF_MEMORY, "session_create: host allocation");
     s->code = code;
@@ -167,8 +276,8 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
     const size_t B = (size_t)max_batch;
     // MAPPED: fine-grained (coherent) pinned memory the kernel reads and writes
     // over the bus; COPY: ordinary pinned staging for the copy engines.
-    const unsigned fl = io_mode == QLDPC_IO_MAPPED ? (hipHostMallocMapped | hipHostMallocCoherent)
-                                                   : hipHostMallocDefault;
+    const bool mapped = io_mode != QLDPC_IO_COPY;
+    const unsigned fl = mapped ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault;
     hipError_t e = hipSetDevice(code->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_syn, B * s->syn_words * 4, fl);
@@ -176,7 +285,7 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_err, B * s->err_words * 4, fl);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_conv, B, fl);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_iters, B, fl);
-    if (e == hipSuccess && io_mode == QLDPC_IO_MAPPED) {
+    if (e == hipSuccess && mapped) {
         e = hipHostGetDevicePointer((void **)&s->m_syn, s->h_syn, 0);
         if (e == hipSuccess) e = hipHostGetDevicePointer(&s->m_prior, s->h_prior, 0);
         if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->m_err, s->h_err, 0);
@@ -190,9 +299,41 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
         if (e == hipSuccess) e = hipMalloc((void **)&s->d_conv, B);
         if (e == hipSuccess) e = hipMalloc((void **)&s->d_iters, B);
     }
+    ResidentRing *m_ring = nullptr;
+    int clock_khz = 0;
+    if (e == hipSuccess && resident) {
+        e = hipHostMalloc((void **)&s->ring, sizeof(ResidentRing), hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess) {
+            std::memset(s->ring, 0, sizeof(ResidentRing));
+            e = hipHostGetDevicePointer((void **)&m_ring, s->ring, 0);
+        }
+        if (e == hipSuccess) e = hipMalloc((void **)&s->d_cmd, 2 * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_exit, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, code->device);
+    }
     if (e != hipSuccess) {
         release(s);
         return set_error(QLDPC_ERR_OUT_OF_MEMORY, std::string("session_create: ") + hipGetErrorString(e));
+    }
+    if (resident) {
+        s->rkey = k;
+        s->rkey.post = 0;
+        s->rargs.a = a;
+        s->rargs.a.syn = s->m_syn;
+        s->rargs.a.prior = s->m_prior;
+        s->rargs.a.err = s->m_err;
+        s->rargs.a.conv = s->m_conv;
+        s->rargs.a.iters = s->m_iters;
+        s->rargs.a.post = nullptr;
+        s->rargs.ring = m_ring;
+        s->rargs.cmd = s->d_cmd;
+        s->rargs.idle_ticks = (uint64_t)(kResidentIdleMs * (clock_khz > 0 ? clock_khz : 100000));
+        st = resident_start(s, 0);
+        if (st != QLDPC_OK) {
+            if (resident_stop(s)) release(s);
+            return st;
+        }
+        s->last_answer = std::chrono::steady_clock::now();
     }
     *out = s;
     return QLDPC_OK;
@@ -200,6 +341,8 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
 
 qldpc_status qldpc_session_destroy(qldpc_session s) {
     if (!s) return QLDPC_OK;
+    if (!resident_stop(s))   // leave the buffers to a grid that still runs rather than free them under it
+        return set_error(QLDPC_ERR_DEVICE, "session_destroy: the resident decoder did not exit; session leaked");
     if (s->stream) hipStreamSynchronize(s->stream);
     release(s);
     return QLDPC_OK;

@@ -3,6 +3,7 @@ CPU oracle (same bar as the wavefront layout: identical decisions, flags and
 iteration counts; FP32 posterior within 1e-5 relative; int8 bit-exact)."""
 import os
 import tempfile
+import time
 
 import numpy as np
 import pytest
@@ -114,7 +115,7 @@ def test_autotune_records_a_valid_choice_and_roundtrips():
         dec2.close()
 
 
-@pytest.mark.parametrize("io_mode", [abi.QLDPC_IO_COPY, abi.QLDPC_IO_MAPPED])
+@pytest.mark.parametrize("io_mode", [abi.QLDPC_IO_COPY, abi.QLDPC_IO_MAPPED, abi.QLDPC_IO_RESIDENT])
 @pytest.mark.parametrize("fmt", [0, 1])
 def test_session_decode_matches_oracle(io_mode, fmt):
     c, H, dec = code(64)
@@ -140,3 +141,47 @@ def test_session_decode_matches_oracle(io_mode, fmt):
               f"p99 {np.percentile(lat, 99):.1f} us")
     finally:
         abi.qldpc_session_destroy(s)
+
+
+@pytest.mark.parametrize("L,fmt,nw,per_bit", [(64, 1, 8, False), (128, 0, 16, True)])
+def test_resident_session_survives_idle_exit(L, fmt, nw, per_bit):
+    """The resident grid leaves after 200 ms without a request and the next
+    request relaunches it; answers before and after equal the oracle's."""
+    c, H, dec = code(L)
+    n = 12
+    b = noise.Batch(c.hz, 41 + L, np.arange(n), 0.05)
+    if fmt == 0:
+        prior = b.gamma
+        if per_bit:
+            j = noise.rng.uniform(41, noise.rng.DOMAIN_PRIOR, np.arange(n)[:, None], np.arange(c.n)[None, :])
+            prior = (b.prior_bits() * (0.5 + j)).astype(np.float32)
+    else:
+        prior = b.gamma_q4()
+    prior = np.ascontiguousarray(prior)
+    syn = np.ascontiguousarray(bits.pack_bits(b.s))
+    o = oracle_decode(H, b.s, prior, fmt=fmt)
+    s = abi.qldpc_session_create(dec.handle, dec.params(fmt=fmt, per_bit=per_bit, waves_per_shot=nw), 8,
+                                 abi.QLDPC_IO_RESIDENT)
+    try:
+        for k, (lo, hi) in enumerate(((0, 8), (8, 9), (9, 12), (0, 8))):
+            if k == 2:
+                time.sleep(0.6)      # longer than the idle time: the grid has left
+            B = hi - lo
+            err = np.zeros((B, dec.err_words), np.uint32)
+            conv = np.full(B, 7, np.uint8)
+            it = np.zeros(B, np.uint8)
+            abi.qldpc_session_decode(s, B, syn[lo:hi], prior[lo:hi], err, conv, it)
+            assert np.array_equal(bits.unpack_bits(err, c.n), o.e[lo:hi]), (k, lo, hi)
+            assert np.array_equal(conv, o.converged[lo:hi]) and np.array_equal(it.astype(np.int32), o.iters[lo:hi])
+    finally:
+        abi.qldpc_session_destroy(s)
+
+
+def test_resident_session_rejects_unsupported_configs():
+    for L, kw, mb, status in ((64, dict(sched=abi.QLDPC_LAYERED), 4, abi.QLDPC_ERR_UNSUPPORTED),
+                              (32, {}, 4, abi.QLDPC_ERR_UNSUPPORTED),
+                              (64, {}, 65, abi.QLDPC_ERR_INVALID_ARG)):
+        c, H, dec = code(L)
+        with pytest.raises(abi.QldpcError) as ei:
+            abi.qldpc_session_create(dec.handle, dec.params(**kw), mb, abi.QLDPC_IO_RESIDENT)
+        assert ei.value.status == status, (L, kw, mb)
