@@ -123,8 +123,13 @@ typedef enum {
     QLDPC_LAYOUT_AUTO = 0,   /* tuned choice for (code, format, batch)       */
     QLDPC_LAYOUT_WAVE = 1,   /* one wavefront decodes one shot (or 64 / L
                                 shots when L < 64); throughput layout        */
-    QLDPC_LAYOUT_BLOCK = 2   /* one workgroup of several wavefronts decodes
+    QLDPC_LAYOUT_BLOCK = 2,  /* one workgroup of several wavefronts decodes
                                 one shot; latency layout                     */
+    QLDPC_LAYOUT_WAVE_REG = 3 /* as WAVE, with every message kept in the
+                                lanes' registers and moved between lanes by
+                                cross-lane permutes instead of LDS; FP32
+                                flooding with L <= 64 only (otherwise
+                                QLDPC_ERR_UNSUPPORTED)                       */
 } qldpc_layout;
 
 typedef struct {

@@ -26,7 +26,7 @@ QLDPC_ERR_NOT_READY = 6
 QLDPC_F32, QLDPC_I8Q4 = 0, 1
 QLDPC_FLOOD, QLDPC_LAYERED = 0, 1
 QLDPC_PRIOR_PER_SHOT, QLDPC_PRIOR_PER_BIT = 0, 1
-QLDPC_LAYOUT_AUTO, QLDPC_LAYOUT_WAVE, QLDPC_LAYOUT_BLOCK = 0, 1, 2
+QLDPC_LAYOUT_AUTO, QLDPC_LAYOUT_WAVE, QLDPC_LAYOUT_BLOCK, QLDPC_LAYOUT_WAVE_REG = 0, 1, 2, 3
 QLDPC_IO_COPY, QLDPC_IO_MAPPED, QLDPC_IO_RESIDENT = 0, 1, 2
 
 

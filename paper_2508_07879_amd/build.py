@@ -29,6 +29,18 @@ FLAGS = [
 ]
 
 
+# Per-file additions.  The register-resident decoders are built without the
+# IEEE-mode NaN quieting of min/max/med3 (which needs a canonicalising
+# instruction per message per iteration); no message is ever NaN, and the
+# flag changes no arithmetic result on other values.
+FILE_FLAGS = {"wreg_": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
+
+
+def _file_flags(src: str) -> list:
+    base = os.path.basename(src)
+    return [f for pre, fl in FILE_FLAGS.items() if base.startswith(pre) for f in fl]
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
@@ -55,7 +67,7 @@ def _compile(src: str, verbose: bool, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if incremental and not _stale(src, obj):
         return obj
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *_file_flags(src), "-x", "hip", "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -55,7 +55,7 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     if (p->prior_mode != QLDPC_PRIOR_PER_SHOT && p->prior_mode != QLDPC_PRIOR_PER_BIT)
         return fail(QLDPC_ERR_INVALID_ARG, "decode: bad prior mode");
     if (!(p->alpha > 0.0f && p->alpha <= 1.0f)) return fail(QLDPC_ERR_INVALID_ARG, "decode: alpha must be in (0, 1]");
-    if (p->layout < QLDPC_LAYOUT_AUTO || p->layout > QLDPC_LAYOUT_BLOCK)
+    if (p->layout < QLDPC_LAYOUT_AUTO || p->layout > QLDPC_LAYOUT_WAVE_REG)
         return fail(QLDPC_ERR_INVALID_ARG, "decode: bad layout");
     if (p->waves_per_shot != 0 && p->waves_per_shot != 8 && p->waves_per_shot != 16)
         return fail(QLDPC_ERR_INVALID_ARG, "decode: waves_per_shot must be 0, 8 or 16");
@@ -101,6 +101,8 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
             return fail(QLDPC_ERR_UNSUPPORTED, "decode: the workgroup layout needs flooding and L >= 64");
         if (nw == 0) nw = 16;
     }
+    if (layout == QLDPC_LAYOUT_WAVE_REG && !(p->fmt == QLDPC_F32 && p->sched == QLDPC_FLOOD && code->L <= 64))
+        return fail(QLDPC_ERR_UNSUPPORTED, "decode: register-resident messages need FP32 flooding and L <= 64");
     key->layout = layout;
     key->nw = nw;
     return QLDPC_OK;
@@ -297,6 +299,8 @@ qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, 
     if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, "autotune: null buffer");
     struct Cand { int layout, nw; };
     std::vector<Cand> cands = {{QLDPC_LAYOUT_WAVE, 0}};
+    if (params->fmt == QLDPC_F32 && params->sched == QLDPC_FLOOD && code->L <= 64)
+        cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});
     if (params->sched == QLDPC_FLOOD && code->L >= 64) {
         cands.push_back({QLDPC_LAYOUT_BLOCK, 8});
         cands.push_back({QLDPC_LAYOUT_BLOCK, 16});
@@ -388,9 +392,11 @@ qldpc_status qldpc_tune_load(qldpc_code code, const char *path) {
     std::lock_guard<std::mutex> g(code->tune_mu);
     for (size_t i = 0; i < nums.size(); i += 4) {
         const int layout = (int)nums[i + 1], nw = (int)nums[i + 2];
-        if (layout != QLDPC_LAYOUT_WAVE && layout != QLDPC_LAYOUT_BLOCK) continue;
+        if (layout != QLDPC_LAYOUT_WAVE && layout != QLDPC_LAYOUT_BLOCK && layout != QLDPC_LAYOUT_WAVE_REG) continue;
         if (layout == QLDPC_LAYOUT_BLOCK && nw != 8 && nw != 16) continue;
-        code->tune[(int)nums[i]] = TuneChoice{layout, nw, (float)nums[i + 3]};
+        const int key = (int)nums[i], fmt = key / 32, sched = (key / 16) % 2;   // see tune_key
+        if (layout == QLDPC_LAYOUT_WAVE_REG && !(fmt == QLDPC_F32 && sched == QLDPC_FLOOD && code->L <= 64)) continue;
+        code->tune[key] = TuneChoice{layout, nw, (float)nums[i + 3]};
     }
     return QLDPC_OK;
 }

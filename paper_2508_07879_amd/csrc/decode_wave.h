@@ -52,6 +52,10 @@ namespace qldpc {
 template <int FMT> struct Knobs;
 template <> struct Knobs<0> { static constexpr int sched_group = 0, vn_batch = 4, wave_cap = 1; };
 template <> struct Knobs<1> { static constexpr int sched_group = 1, vn_batch = 2, wave_cap = 4; };
+// Register-resident FP32 messages (see wave_decode): one block column at a
+// time keeps the scalar working set (shifts, rotated ballots) within the
+// scalar register file.
+struct RegKnobs { static constexpr int sched_group = 0, vn_batch = 1; };
 
 template <int FMT>
 __device__ __forceinline__ void sched_group_end(int idx) {
@@ -77,14 +81,16 @@ template <int FMT> struct Fmt;
 template <> struct Fmt<0> { using msg_t = float; using q_t = float; using prior_t = float; };
 template <> struct Fmt<1> { using msg_t = int8_t; using q_t = int16_t; using prior_t = int8_t; };
 
-template <class S, int L, int FMT, int SCHED, int NG = 1>
+// LDS of one wave.  REG: messages live in registers; only the staging of
+// the packed decisions remains.
+template <class S, int L, int FMT, int SCHED, int NG = 1, bool REG = false>
 struct WaveLds {
     using G = Geo<S, L>;
     using msg_t = typename Fmt<FMT>::msg_t;
     using q_t = typename Fmt<FMT>::q_t;
     static constexpr int H = L <= 64 ? NG : L / 64;
     static constexpr int ROW = 64 * H;
-    static constexpr int MSG = S::SLOTS * ROW;
+    static constexpr int MSG = REG ? 0 : S::SLOTS * ROW;
     static constexpr int QN = SCHED == 1 ? S::NB * ROW : 0;
     static constexpr size_t msg_bytes = MSG * sizeof(msg_t);
     static constexpr size_t q_off = (msg_bytes + 15) & ~size_t(15);
@@ -158,8 +164,11 @@ __device__ __forceinline__ void cn_f32(float (&v)[DC], uint32_t P, float alpha) 
     }
 #pragma unroll
     for (int j = 0; j < DC; ++j) P ^= fbits(v[j]);
-    const float A1 = alpha * m1;
-    const float A2 = alpha * m2;
+    float A1 = alpha * m1;
+    float A2 = alpha * m2;
+    // two products per check: keep the compiler from moving the multiply
+    // behind the per-edge select below (one product per edge)
+    asm volatile("" : "+v"(A1), "+v"(A2));
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
         // |q_j| == min1: j is the (or a tied) minimum; the excluded minimum is
@@ -195,6 +204,11 @@ __device__ __forceinline__ void cn_i8(int (&v)[DC], uint32_t P, int num, int sh)
 }
 
 __device__ __forceinline__ int sat127(int x) { return min(127, max(-127, x)); }
+
+// The value `v` held by the lane whose byte address (4 * lane) is `addr`.
+__device__ __forceinline__ float bperm(int addr, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
 
 }  // namespace wave
 
@@ -251,19 +265,29 @@ struct ShotRef {
 // The decoder body.  A lane owns H "halves": for L = 128 the two circulant
 // rows t and t + 64 of one shot; for L <= 64, NG independent 64-lane groups,
 // each decoding its own 64 / L shots (ref[h] describes group h's segment of
-// this lane).  `lds` points to WaveLds<S, L, FMT, SCHED, NG>::bytes.
+// this lane).  `lds` points to WaveLds<S, L, FMT, SCHED, NG, REG>::bytes.
+//
+// REG (FP32 flooding, L <= 64, one group): the lane's entry of every slot
+// row is kept in a register array m[slot] instead of LDS.  The check pass
+// then works on registers only; the variable pass fetches the entry a
+// variable reaches through a block of shift s from lane (t - s) mod L with a
+// cross-lane permute (ds_bpermute) and returns its new message to lane
+// (t + s) mod L the same way.  Values and the order of every operation are
+// those of the LDS form; only where the messages are kept differs.
 // ---------------------------------------------------------------------------
-template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED, int NG>
+template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED, int NG, bool REG = false>
 __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *__restrict__ code,
                                             const ShotRef (&ref)[NG], unsigned char *lds) {
     using namespace wave;
     using G = Geo<S, L>;
-    using Lay = WaveLds<S, L, FMT, SCHED, NG>;
+    using Lay = WaveLds<S, L, FMT, SCHED, NG, REG>;
     using msg_t = typename Fmt<FMT>::msg_t;
     using q_t = typename Fmt<FMT>::q_t;
     using prior_t = typename Fmt<FMT>::prior_t;
     using acc_t = typename std::conditional<FMT == 0, float, int>::type;
     static_assert(L <= 64 || NG == 1, "L = 128 uses both halves for one shot");
+    static_assert(!REG || (FMT == 0 && SCHED == 0 && !WEIGHTED && L <= 64 && NG == 1),
+                  "register-resident messages: FP32 flooding, L <= 64, one group");
     constexpr bool GRP = L <= 64;                 // halves are independent groups
     constexpr int H = GRP ? NG : L / 64;          // halves per lane
     constexpr int MB = S::MB, NB = S::NB, DC = S::DC, ROW = 64 * H;
@@ -286,6 +310,30 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     auto cn_at = [&](int h, uint32_t s) -> int {
         if constexpr (GRP) return 64 * h + ((int)(((uint32_t)lane + s) & (uint32_t)(L - 1)) | (lane & ~(L - 1)));
         else return (int)(((uint32_t)(lane + 64 * h) + s) & (uint32_t)(L - 1));
+    };
+    // REG: messages in registers, shifts read as scalars, and the byte
+    // addresses of the lanes (t - s) and (t + s) mod L within the segment.
+    // The table pointer is re-derived opaquely for every batch of block
+    // columns, so the compiler reloads each batch's shifts (scalar-cache
+    // hits) instead of hoisting all 120 out of the loop into scalar registers
+    // it does not have.
+    float m[REG ? S::SLOTS : 1];
+    const uint32_t lane4 = (uint32_t)lane << 2;
+    CodePtr cpb = const_code(code);
+    auto reload_table = [&]() {
+        uint64_t v = (uint64_t)code;
+        asm volatile("" : "+s"(v));
+        cpb = (CodePtr)v;
+    };
+    auto shift_of = [&](int slot) -> uint32_t {
+        if constexpr (REG) return (uint32_t)cpb->shift[slot];
+        else return (uint32_t)code->shift[slot];
+    };
+    auto vn_src = [&](uint32_t s) -> int {
+        return (int)(((lane4 - (s << 2)) & (uint32_t)(4 * L - 4)) | (lane4 & ~(uint32_t)(4 * L - 1)));
+    };
+    auto cn_src = [&](uint32_t s) -> int {
+        return (int)(((lane4 + (s << 2)) & (uint32_t)(4 * L - 4)) | (lane4 & ~(uint32_t)(4 * L - 1)));
     };
 
     bool valid[NG];
@@ -339,9 +387,14 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
             static_for<0, S::T.col_deg[C]>([&](auto Ii) {
                 constexpr int i = decltype(Ii)::value;
                 constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
-                const uint32_t s = (uint32_t)code->shift[slot];
+                const uint32_t s = shift_of(slot);
+                if constexpr (REG) {
+                    // the check at position t of this slot sees variable t + s
+                    m[slot] = PER_BIT ? bperm(cn_src(s), gamma_of(C, 0)) : gamma_of(C, 0);
+                } else {
 #pragma unroll
-                for (int h = 0; h < H; ++h) msg[slot * ROW + vn_at(h, s)] = (msg_t)gamma_of(C, h);
+                    for (int h = 0; h < H; ++h) msg[slot * ROW + vn_at(h, s)] = (msg_t)gamma_of(C, h);
+                }
             });
         });
     } else {
@@ -381,7 +434,8 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                     if constexpr (FMT == 0) {
                         float v[DC];
 #pragma unroll
-                        for (int j = 0; j < DC; ++j) v[j] = msg[(R * DC + j) * ROW + lane + 64 * h];
+                        for (int j = 0; j < DC; ++j)
+                            v[j] = REG ? m[R * DC + j] : msg[(R * DC + j) * ROW + lane + 64 * h];
                         if constexpr (WEIGHTED) {
                             float wj[DC];
                             load_weights<L, DC>(a.weights, k - 1, MB * L * DC, R, p + posoff(h), wj);
@@ -390,7 +444,10 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                             cn_f32<DC>(v, P, a.alpha);
                         }
 #pragma unroll
-                        for (int j = 0; j < DC; ++j) msg[(R * DC + j) * ROW + lane + 64 * h] = v[j];
+                        for (int j = 0; j < DC; ++j) {
+                            if constexpr (REG) m[R * DC + j] = v[j];
+                            else msg[(R * DC + j) * ROW + lane + 64 * h] = v[j];
+                        }
                     } else {
                         int v[DC];
 #pragma unroll
@@ -457,10 +514,11 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
         // loads of a batch overlap instead of each column waiting for the
         // previous column's stores (the compiler cannot prove that rotated
         // addresses of different columns never alias).
-        constexpr int VB = Knobs<FMT>::vn_batch;
+        constexpr int VB = REG ? RegKnobs::vn_batch : Knobs<FMT>::vn_batch;
         static_for<0, (NB + VB - 1) / VB>([&](auto Bc) {
             constexpr int C0 = decltype(Bc)::value * VB;
             constexpr int NC = (C0 + VB <= NB) ? VB : NB - C0;
+            if constexpr (REG) reload_table();
             acc_t rr[NC][H][kMaxDv];
             int ii[NC][H][kMaxDv];
             if constexpr (SCHED == 0) {
@@ -472,8 +530,12 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                         static_for<0, S::T.col_deg[C]>([&](auto Ii) {
                             constexpr int i = decltype(Ii)::value;
                             constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
-                            ii[kc][h][i] = slot * ROW + vn_at(h, (uint32_t)code->shift[slot]);
-                            rr[kc][h][i] = (acc_t)msg[ii[kc][h][i]];
+                            if constexpr (REG) {
+                                rr[kc][h][i] = bperm(vn_src(shift_of(slot)), m[slot]);
+                            } else {
+                                ii[kc][h][i] = slot * ROW + vn_at(h, (uint32_t)code->shift[slot]);
+                                rr[kc][h][i] = (acc_t)msg[ii[kc][h][i]];
+                            }
                         });
                     }
                 });
@@ -492,7 +554,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                         if constexpr (FMT == 0) {
                             // prefix sums from gamma in increasing check order; the
                             // excluded sum of edge i continues the prefix before i
-                            float pre[d + 1];
+                            float pre[d + 1], qv[d];
                             pre[0] = gamma_of(C, h);
 #pragma unroll
                             for (int i = 0; i < d; ++i) pre[i + 1] = pre[i] + r[i];
@@ -501,7 +563,17 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                                 float q = pre[i];
 #pragma unroll
                                 for (int j = i + 1; j < d; ++j) q = q + r[j];
-                                msg[idx[i]] = q;
+                                qv[i] = q;
+                            }
+                            if constexpr (REG) {
+                                static_for<0, d>([&](auto Ii) {
+                                    constexpr int i = decltype(Ii)::value;
+                                    constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
+                                    m[slot] = bperm(cn_src(shift_of(slot)), qv[i]);
+                                });
+                            } else {
+#pragma unroll
+                                for (int i = 0; i < d; ++i) msg[idx[i]] = qv[i];
                             }
                             Q = pre[d];
                         } else {
@@ -525,10 +597,11 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                     constexpr int i = decltype(Ii)::value;
                     constexpr int R = S::T.col_R[C][i];
                     constexpr int slot = R * DC + S::T.col_j[C][i];
-                    const uint32_t s = (uint32_t)code->shift[slot];
+                    const uint32_t s = shift_of(slot);
                     if constexpr (GRP) {
+                        const uint64_t low = REG ? cpb->lowmask[slot] : code->lowmask[slot];
 #pragma unroll
-                        for (int h = 0; h < H; ++h) acc[R][h] ^= seg_rotr<L>(mask[h], s, code->lowmask[slot]);
+                        for (int h = 0; h < H; ++h) acc[R][h] ^= seg_rotr<L>(mask[h], s, low);
                     } else {
                         uint64_t lo, hi;
                         rotr128(mask[0], mask[H - 1], s, lo, hi);
@@ -537,7 +610,12 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                     }
                 });
             });
-            sched_group_end<FMT>(decltype(Bc)::value);
+            if constexpr (REG) {
+                if constexpr (RegKnobs::sched_group > 0)
+                    if ((decltype(Bc)::value + 1) % RegKnobs::sched_group == 0) __builtin_amdgcn_sched_barrier(0);
+            } else {
+                sched_group_end<FMT>(decltype(Bc)::value);
+            }
         });
 
         // ---------------- stopping rule, outputs ------------------------------
@@ -649,6 +727,39 @@ void k_wave(const DecodeArgs a) {
     ref[0].syn = a.syn + (shot < a.batch ? shot : 0) * G::SW;
     ref[0].err = a.err + (shot < a.batch ? shot : 0) * G::EW;
     wave_decode<S, L, FMT, SCHED, PER_BIT, POST, WEIGHTED, 1>(a, a.code, ref, lds);
+}
+
+// Register-resident FP32 flooding (L <= 64): LDS holds only the decision
+// staging, so occupancy is set by registers; two waves per SIMD leave 256
+// VGPRs per lane for the 120 message registers and the working set.
+template <class S, int L, bool PER_BIT, bool POST>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+void k_wreg(const DecodeArgs a) {
+    using G = Geo<S, L>;
+    using Lay = WaveLds<S, L, 0, 0, 1, true>;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
+    const int g = (threadIdx.x & 63) / G::SEG;
+    const long shot = (long)blockIdx.x * G::SPW + g;
+    ShotRef ref[1];
+    ref[0].shot = shot < a.batch ? shot : -1;
+    ref[0].syn = a.syn + (shot < a.batch ? shot : 0) * G::SW;
+    ref[0].err = a.err + (shot < a.batch ? shot : 0) * G::EW;
+    wave_decode<S, L, 0, 0, PER_BIT, POST, false, 1, true>(a, a.code, ref, lds);
+}
+
+template <class S, int L>
+hipError_t launch_wreg(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
+    if (k.fmt != 0 || k.sched != 0) return hipErrorNotSupported;
+    using G = Geo<S, L>;
+    const unsigned grid = (unsigned)((a.batch + G::SPW - 1) / G::SPW);
+    if (k.per_bit) {
+        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, true, true>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_wreg<S, L, true, false>), dim3(grid), dim3(64), 0, st, a);
+    } else {
+        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, false, true>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_wreg<S, L, false, false>), dim3(grid), dim3(64), 0, st, a);
+    }
+    return hipGetLastError();
 }
 
 template <class S, int L, int FMT, int SCHED, bool PB, bool PO>

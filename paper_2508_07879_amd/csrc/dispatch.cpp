@@ -9,6 +9,9 @@ hipError_t launch_wave_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wave_L128(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_block_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_block_L128(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_wreg_L16(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_wreg_L32(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_wreg_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_resident_L64(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
 hipError_t launch_resident_L128(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
 
@@ -25,6 +28,14 @@ hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t st
     if (k.layout == 2) {
         if (k.L == 64) return launch_block_L64(k, a, stream);
         if (k.L == 128) return launch_block_L128(k, a, stream);
+    }
+    if (k.layout == 3) {
+        switch (k.L) {
+            case 16: return launch_wreg_L16(k, a, stream);
+            case 32: return launch_wreg_L32(k, a, stream);
+            case 64: return launch_wreg_L64(k, a, stream);
+            default: break;
+        }
     }
     return hipErrorNotSupported;
 }

@@ -1,0 +1,11 @@
+// Instantiations of the register-resident wavefront decoder for L = 32.
+#include "decode_wave.h"
+
+namespace qldpc {
+
+hipError_t launch_wreg_L32(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
+    if (k.which != 0) return hipErrorNotSupported;
+    return launch_wreg<ShapeLP35Z, 32>(k, a, st);
+}
+
+}  // namespace qldpc

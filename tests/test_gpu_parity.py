@@ -32,7 +32,7 @@ def code(L):
 
 
 def run_case(L, shots, p, fmt=0, sched=0, per_bit=False, seed=7, max_iters=32, early_stop=True,
-             alpha=0.75, syn=None):
+             alpha=0.75, syn=None, layout=abi.QLDPC_LAYOUT_WAVE):
     c, H, dec = code(L)
     b = noise.Batch(c.hz, seed, np.arange(shots), p)
     s = b.s if syn is None else syn
@@ -53,10 +53,10 @@ def run_case(L, shots, p, fmt=0, sched=0, per_bit=False, seed=7, max_iters=32, e
         prior = q
         scale = None
     g = gpu_decode(dec, s, prior, fmt=fmt, sched=sched, max_iters=max_iters, early_stop=early_stop,
-                   per_bit=per_bit, alpha=alpha, layout=abi.QLDPC_LAYOUT_WAVE)
+                   per_bit=per_bit, alpha=alpha, layout=layout)
     o = oracle_decode(H, s, prior, fmt=fmt, sched=sched, max_iters=max_iters, early_stop=early_stop,
                       layer_size=L, alpha=alpha)
-    assert_parity(g, o, scale, fmt, tag=f"L={L} p={p} fmt={fmt} sched={sched} pb={per_bit}")
+    assert_parity(g, o, scale, fmt, tag=f"L={L} p={p} fmt={fmt} sched={sched} pb={per_bit} layout={layout}")
     return g, o
 
 
@@ -151,8 +151,45 @@ def test_invalid_arguments():
     assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("fmt,sched", [(0, 0), (1, 0), (0, 1), (1, 1)])
-def test_full_batch_sampled(fmt, sched):
+REG = abi.QLDPC_LAYOUT_WAVE_REG
+
+
+@pytest.mark.parametrize("L", [16, 32, 64])
+@pytest.mark.parametrize("per_bit", [False, True])
+def test_register_resident_layout(L, per_bit):
+    """Messages in registers, moved between lanes by permutes: the same
+    decisions, flags, iteration counts and posteriors as the oracle."""
+    run_case(L, 300 if L < 64 else 130, 0.05, per_bit=per_bit, seed=17, layout=REG)
+    run_case(L, 200, 0.02, per_bit=per_bit, seed=18, layout=REG)
+
+
+def test_register_resident_edge_cases():
+    run_case(64, 40, 0.05, max_iters=10, early_stop=False, seed=19, layout=REG)
+    g, _ = run_case(16, 37, 0.05, max_iters=1, seed=20, layout=REG)          # ragged: 37 = 9 waves + 1 shot
+    assert np.all(g[2] == 1)
+    run_case(32, 33, 0.04, alpha=1.0, seed=21, layout=REG)                   # ragged: 16 waves + 1 shot
+    run_case(64, 50, 0.03, alpha=0.5, seed=22, layout=REG)
+    c, H, dec = code(64)
+    g, _ = run_case(64, 3, 0.03, syn=np.zeros((3, c.hz.m), np.uint8), seed=23, layout=REG)
+    assert np.all(g[1] == 1) and np.all(g[2] == 1)
+
+
+def test_register_resident_rejects_unsupported():
+    for L, fmt, sched in ((64, 1, 0), (64, 0, 1), (128, 0, 0)):
+        c, H, dec = code(L)
+        p = dec.params(fmt=fmt, sched=sched, layout=REG)
+        err, conv, it, _ = dec.outputs(2)
+        syn = torch.zeros((2, dec.syn_words), dtype=torch.int32, device="cuda")
+        pr = torch.ones(2, device="cuda") if fmt == 0 else torch.ones(2, dtype=torch.int8, device="cuda")
+        with pytest.raises(abi.QldpcError) as ei:
+            abi.qldpc_decode_batch(dec.handle, p, 2, syn, pr, err, conv, it, None)
+        assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED, (L, fmt, sched)
+
+
+@pytest.mark.parametrize("fmt,sched,layout", [(0, 0, abi.QLDPC_LAYOUT_WAVE), (1, 0, abi.QLDPC_LAYOUT_WAVE),
+                                              (0, 1, abi.QLDPC_LAYOUT_WAVE), (1, 1, abi.QLDPC_LAYOUT_WAVE),
+                                              (0, 0, abi.QLDPC_LAYOUT_WAVE_REG)])
+def test_full_batch_sampled(fmt, sched, layout):
     """65536 shots at L = 64, p = 0.05, as the benchmark launches them; the
     oracle re-decodes a sample of shots one by one, and every converged shot
     must reproduce its syndrome."""
@@ -160,7 +197,7 @@ def test_full_batch_sampled(fmt, sched):
     B = 65536
     b = noise.Batch(c.hz, 1000 + fmt + 2 * sched, np.arange(B), 0.05)
     prior = b.gamma if fmt == 0 else b.gamma_q4()
-    g = gpu_decode(dec, b.s, prior, fmt=fmt, sched=sched, posterior=False, layout=abi.QLDPC_LAYOUT_WAVE)
+    g = gpu_decode(dec, b.s, prior, fmt=fmt, sched=sched, posterior=False, layout=layout)
     e, conv, it, _ = g
     ok = conv == 1
     assert np.array_equal(noise.syndromes(c.hz, e[ok]), b.s[ok])
