@@ -53,7 +53,7 @@ def recorded_traffic(kernel_sources):
     """HBM bytes per launch from the committed counter summary, or None when
     the kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_k_wave_f32_flood_L64.json")
+    path = os.path.join(ROOT, "profiles", "traffic_k_wreg_f32_flood_L64.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
@@ -109,8 +109,8 @@ def main():
 
     stream = torch.cuda.current_stream()
 
-    def run(fmt, sched, timed_events=None):
-        prm = dec.params(fmt=fmt, sched=sched, max_iters=32, early_stop=True)
+    def run(fmt, sched, timed_events=None, layout=abi.QLDPC_LAYOUT_WAVE):
+        prm = dec.params(fmt=fmt, sched=sched, max_iters=32, early_stop=True, layout=layout)
         for j, bb in enumerate(batches):
             pr = bb["g32"] if fmt == abi.QLDPC_F32 else bb["g8"]
             if timed_events is not None:
@@ -119,16 +119,16 @@ def main():
             if timed_events is not None:
                 timed_events[j][1].record(stream)
 
-    def measure(fmt, sched, steps, warmup):
+    def measure(fmt, sched, steps, warmup, layout=abi.QLDPC_LAYOUT_WAVE):
         for _ in range(warmup):
-            run(fmt, sched)
+            run(fmt, sched, layout=layout)
         torch.cuda.synchronize()
         ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
                for _ in P_LIST] for _ in range(steps)]
         torch.cuda.synchronize()
         t = time.perf_counter()
         for s in range(steps):
-            run(fmt, sched, ev[s])
+            run(fmt, sched, ev[s], layout=layout)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
         kms = np.array([[e[0].elapsed_time(e[1]) for e in step] for step in ev])  # [steps, 3] ms
@@ -136,7 +136,10 @@ def main():
         return wall, kms, its
 
     # ---------------- headline: FP32 flooding --------------------------------
-    wall, kms, its = measure(abi.QLDPC_F32, abi.QLDPC_FLOOD, args.steps, args.warmup)
+    # the register-resident layout (messages in VGPRs) is the fastest for
+    # FP32 flooding at L <= 64; the LDS layout is reported among the variants
+    head_layout = abi.QLDPC_LAYOUT_WAVE_REG if args.L <= 64 else abi.QLDPC_LAYOUT_WAVE
+    wall, kms, its = measure(abi.QLDPC_F32, abi.QLDPC_FLOOD, args.steps, args.warmup, layout=head_layout)
     syn_per_step = B * len(P_LIST)
     value = syn_per_step * args.steps / wall
     ms_per_step = wall * 1e3 / args.steps
@@ -175,8 +178,8 @@ def main():
     # ---------------- other formats and schedules ----------------------------
     variants = {}
     if not args.no_variants:
-        for name, fmt, sched, bpm in (("int8_flood", 1, 0, 1), ("f32_layered", 0, 1, 4),
-                                      ("int8_layered", 1, 1, 1)):
+        for name, fmt, sched, bpm in (("f32_flood_lds_layout", 0, 0, 4), ("int8_flood", 1, 0, 1),
+                                      ("f32_layered", 0, 1, 4), ("int8_layered", 1, 1, 1)):
             w, k_, it_ = measure(fmt, sched, max(3, args.steps // 4), 1)
             st = max(3, args.steps // 4)
             variants[name] = dict(
@@ -299,7 +302,9 @@ def main():
                         f"H_Z syndromes of iid X flips, p in {list(P_LIST)}, {B} shots per batch; "
                         "normalized min-sum alpha=0.75, flooding, <=32 iterations, early stop, FP32",
             "batch": B, "noise_rates": list(P_LIST), "max_iters": 32, "alpha": 0.75,
-            "schedule": "flooding", "layout": "wavefront per shot, messages in LDS",
+            "schedule": "flooding",
+            "layout": ("wavefront per shot, messages in registers, cross-lane permutes"
+                       if head_layout == abi.QLDPC_LAYOUT_WAVE_REG else "wavefront per shot, messages in LDS"),
         },
         "roofline": {
             "bound": "alu",
@@ -313,11 +318,14 @@ def main():
                      "events on the decode stream); peak = 256 CU x 64 lanes x 2.4 GHz",
             "kernel_ms_per_launch": {str(p): float(m) for p, m in zip(P_LIST, mean_kernel_ms)},
             "shot_iters_per_s": shot_iters_per_s,
+            "kernel": ("k_wreg<ShapeLP35Z, %d, false, false>" if head_layout == abi.QLDPC_LAYOUT_WAVE_REG
+                       else "k_wave<ShapeLP35Z, %d, 0, 0, false, false, false>") % args.L,
         },
         "hbm_edge_model": {
             "achieved_GBps": achieved_gbs, "peak_GBps": HBM_PEAK_GBS, "frac": achieved_gbs / HBM_PEAK_GBS,
             "model": "4*E*4 B per executed shot-iteration (every edge message read and written in "
-                     "both passes) + 398 B I/O per shot; the kernel keeps these bytes in LDS",
+                     "both passes) + 398 B I/O per shot; the kernel keeps these bytes in registers "
+                     "(LDS in the comparison layout), so HBM carries only the I/O",
         },
         "latency_us": latency,
         "mixed_batch": mixed,

@@ -94,7 +94,11 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
                 found = true;
             }
         }
-        if (!found) layout = (block_ok && batch < 512) ? QLDPC_LAYOUT_BLOCK : QLDPC_LAYOUT_WAVE;
+        const bool reg_ok = p->fmt == QLDPC_F32 && p->sched == QLDPC_FLOOD && code->L <= 64;
+        if (!found)
+            layout = (block_ok && batch < 512) ? QLDPC_LAYOUT_BLOCK
+                     : reg_ok                  ? QLDPC_LAYOUT_WAVE_REG
+                                               : QLDPC_LAYOUT_WAVE;
     }
     if (layout == QLDPC_LAYOUT_BLOCK) {
         if (!block_ok)

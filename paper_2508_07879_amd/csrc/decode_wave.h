@@ -329,11 +329,15 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
         if constexpr (REG) return (uint32_t)cpb->shift[slot];
         else return (uint32_t)code->shift[slot];
     };
+    // (ds_bpermute selects lane (address / 4) mod 64 and ignores the higher
+    // address bits, so for L = 64 the wrap needs no mask.)
     auto vn_src = [&](uint32_t s) -> int {
-        return (int)(((lane4 - (s << 2)) & (uint32_t)(4 * L - 4)) | (lane4 & ~(uint32_t)(4 * L - 1)));
+        if constexpr (L == 64) return (int)(lane4 - (s << 2));
+        else return (int)(((lane4 - (s << 2)) & (uint32_t)(4 * L - 4)) | (lane4 & ~(uint32_t)(4 * L - 1)));
     };
     auto cn_src = [&](uint32_t s) -> int {
-        return (int)(((lane4 + (s << 2)) & (uint32_t)(4 * L - 4)) | (lane4 & ~(uint32_t)(4 * L - 1)));
+        if constexpr (L == 64) return (int)(lane4 + (s << 2));
+        else return (int)(((lane4 + (s << 2)) & (uint32_t)(4 * L - 4)) | (lane4 & ~(uint32_t)(4 * L - 1)));
     };
 
     bool valid[NG];
@@ -730,10 +734,15 @@ void k_wave(const DecodeArgs a) {
 }
 
 // Register-resident FP32 flooding (L <= 64): LDS holds only the decision
-// staging, so occupancy is set by registers; two waves per SIMD leave 256
-// VGPRs per lane for the 120 message registers and the working set.
+// staging, so occupancy is set by registers.  With per-shot priors and no
+// posterior output the working set beside the 120 message registers fits
+// three waves per SIMD (168 VGPRs; the only spills are outside the iteration
+// loop); per-bit priors or posteriors need two (256 VGPRs).
+template <bool PER_BIT, bool POST>
+constexpr int reg_waves() { return (!PER_BIT && !POST) ? 3 : 2; }
+
 template <class S, int L, bool PER_BIT, bool POST>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(reg_waves<PER_BIT, POST>())))
 void k_wreg(const DecodeArgs a) {
     using G = Geo<S, L>;
     using Lay = WaveLds<S, L, 0, 0, 1, true>;
