@@ -255,9 +255,12 @@ typedef struct qldpc_mixed_s *qldpc_mixed;
 
 /* Plan over 1..8 code objects on one device for batches of up to
  * max_batch shots (FP32 flooding, per-shot priors; params gives alpha,
- * iterations and early stop).  Allocates 4 * (max_batch + 17) bytes of
- * device scratch.  use_graph = 1: every distinct argument set is captured
- * once as a hipGraph (bucketing kernels + persistent decoder) and replayed. */
+ * iterations and early stop; lifts 16, 32, 64 and 128).  Allocates
+ * 4 * (max_batch + 20) bytes of device scratch.  One persistent grid per lift
+ * size decodes its shots: messages in registers for L <= 64, in LDS for
+ * L = 128.  use_graph = 1: every distinct argument set is captured
+ * once as a hipGraph (bucketing kernels + persistent decoders) and
+ * replayed. */
 qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const qldpc_decode_params *params,
                                 int32_t max_batch, int32_t use_graph, qldpc_mixed *out);
 qldpc_status qldpc_mixed_destroy(qldpc_mixed plan);
@@ -275,8 +278,9 @@ qldpc_status qldpc_mixed_decode(qldpc_mixed plan, int32_t batch, const int32_t *
                                 const float *priors, uint32_t *errors, uint8_t *converged,
                                 uint8_t *iters_used, void *stream);
 
-/* Times the persistent grid at 2, 4, 8 and 16 wavefronts per compute unit
- * on the caller's batch, keeps the fastest in the plan and returns it. */
+/* Times the register-resident persistent grid (codes with L <= 64) at 6,
+ * 12, 24 and 48 wavefronts per compute unit on the caller's batch, keeps
+ * the fastest in the plan and returns it. */
 qldpc_status qldpc_mixed_autotune(qldpc_mixed plan, int32_t batch, const int32_t *shot_code,
                                   const int64_t *syn_off, const int64_t *err_off, const uint32_t *syndromes,
                                   const float *priors, uint32_t *errors, uint8_t *converged,

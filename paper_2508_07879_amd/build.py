@@ -29,11 +29,13 @@ FLAGS = [
 ]
 
 
-# Per-file additions.  The register-resident decoders are built without the
+# Per-file additions.  The register-resident decoders (single-code and
+# mixed-code) are built without the
 # IEEE-mode NaN quieting of min/max/med3 (which needs a canonicalising
 # instruction per message per iteration); no message is ever NaN, and the
 # flag changes no arithmetic result on other values.
-FILE_FLAGS = {"wreg_": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
+FILE_FLAGS = {"wreg_": ["-fno-honor-nans", "-mno-amdgpu-ieee"],
+              "mixed": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
 
 
 def _file_flags(src: str) -> list:

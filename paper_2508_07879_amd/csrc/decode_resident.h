@@ -25,12 +25,7 @@ __device__ __forceinline__ uint64_t sys_load(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// The value of lane 0, as a wave-uniform (scalar) value.
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
+using wave::uniform64;
 
 // Every branch that decides whether a wave reaches a barrier depends only on
 // wave-uniform values (scalar registers): the whole of wave 0 polls, and

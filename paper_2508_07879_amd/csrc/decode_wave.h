@@ -205,6 +205,13 @@ __device__ __forceinline__ void cn_i8(int (&v)[DC], uint32_t P, int num, int sh)
 
 __device__ __forceinline__ int sat127(int x) { return min(127, max(-127, x)); }
 
+// The value of lane 0, as a wave-uniform (scalar) value.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // The value `v` held by the lane whose byte address (4 * lane) is `addr`.
 __device__ __forceinline__ float bperm(int addr, float v) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));

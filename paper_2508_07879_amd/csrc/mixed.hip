@@ -16,7 +16,9 @@ struct qldpc_mixed_s {
     int32_t ncodes = 0, max_batch = 0, use_graph = 0, device = 0;
     qldpc_code codes[kMaxMixCodes] = {};
     qldpc_decode_params params{};
-    int32_t waves = 0;              // persistent grid size
+    int32_t waves = 0;              // persistent grid size for each lift L <= 64 (registers)
+    int32_t waves128 = 0;           // and for L = 128 (LDS)
+    bool has_L[mix::kMixGrids] = {};
     int32_t *scratch = nullptr;     // device
     std::mutex mu;
     std::map<std::tuple<int32_t, const void *, const void *, const void *, const void *, const void *, const void *,
@@ -61,7 +63,11 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
     hipLaunchKernelGGL(k_mix_clear, dim3(1), dim3(64), 0, st, m);
     hipLaunchKernelGGL(k_mix_count, dim3(nb), dim3(256), 0, st, m);
     hipLaunchKernelGGL(k_mix_scatter, dim3(nb), dim3(256), 0, st, m);
-    hipLaunchKernelGGL(k_mix_decode<ShapeLP35Z>, dim3((unsigned)waves), dim3(64), 0, st, m);
+    // one persistent grid per lift size present, largest L first (bucket order)
+    if (x->has_L[3]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 128>), dim3((unsigned)x->waves128), dim3(64), 0, st, m);
+    if (x->has_L[2]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 64>), dim3((unsigned)waves), dim3(64), 0, st, m);
+    if (x->has_L[1]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 32>), dim3((unsigned)waves), dim3(64), 0, st, m);
+    if (x->has_L[0]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 16>), dim3((unsigned)waves), dim3(64), 0, st, m);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "mixed_decode: launch");
     return QLDPC_OK;
@@ -95,9 +101,18 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
     x->params = *params;
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
-    x->waves = 4 * cus;   // two 61 KB waves fit per CU; two rounds of them by default
+    x->waves = 12 * cus;     // register grids: up to three waves per SIMD
+    x->waves128 = 4 * cus;   // L = 128: two 61 KB waves fit per CU; two rounds
+    for (int c = 0; c < ncodes; ++c) {
+        const int L = codes[c]->L;
+        if (L != 16 && L != 32 && L != 64 && L != 128) {
+            delete x;
+            return set_error(QLDPC_ERR_UNSUPPORTED, "mixed_create: lifts 16, 32, 64 and 128 only");
+        }
+        x->has_L[mix::grid_of(L)] = true;
+    }
     hipError_t e = hipSetDevice(x->device);
-    if (e == hipSuccess) e = hipMalloc(&x->scratch, sizeof(int32_t) * (2 * kMaxMixCodes + 1 + (size_t)max_batch));
+    if (e == hipSuccess) e = hipMalloc(&x->scratch, sizeof(int32_t) * (mix::kScratchHead + (size_t)max_batch));
     if (e != hipSuccess) {
         delete x;
         return set_error(QLDPC_ERR_OUT_OF_MEMORY, "mixed_create: scratch allocation");
@@ -184,7 +199,7 @@ qldpc_status qldpc_mixed_autotune(qldpc_mixed x, int32_t batch, const int32_t *s
     float best = 1e30f;
     int bw = x->waves;
     qldpc_status rc = QLDPC_OK;
-    for (int mult : {2, 4, 8, 16}) {
+    for (int mult : {6, 12, 24, 48}) {
         const int w = mult * cus;
         rc = enqueue(x, batch, shot_code, syn_off, err_off, syn, prior, err, conv, iters, st, w);
         if (rc != QLDPC_OK) break;
