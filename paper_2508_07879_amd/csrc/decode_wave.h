@@ -724,6 +724,17 @@ constexpr int wave_occupancy() {
     return per_simd < 1 ? 1 : (per_simd > cap ? cap : per_simd);
 }
 
+// Workgroups go to the 8 XCDs of the chip in turn (workgroup b to XCD
+// b mod 8), each XCD with its own L2.  Giving every XCD one contiguous range
+// of wave indices puts neighbouring shots, which share cache lines of the
+// packed syndromes and error words, behind one L2.  A bijection of [0, G)
+// for any grid size G.
+__device__ __forceinline__ long xcd_wave_index(long b, long G) {
+    constexpr long X = 8;
+    const long q = G / X, r = G % X, x = b % X;
+    return x * q + (x < r ? x : r) + b / X;
+}
+
 // One wave per workgroup; grid = ceil(batch / shots-per-wave).
 template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<S, L, FMT, SCHED>())))
@@ -732,7 +743,7 @@ void k_wave(const DecodeArgs a) {
     using Lay = WaveLds<S, L, FMT, SCHED, 1>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
     const int g = (threadIdx.x & 63) / G::SEG;
-    const long shot = (long)blockIdx.x * G::SPW + g;
+    const long shot = xcd_wave_index(blockIdx.x, gridDim.x) * G::SPW + g;
     ShotRef ref[1];
     ref[0].shot = shot < a.batch ? shot : -1;
     ref[0].syn = a.syn + (shot < a.batch ? shot : 0) * G::SW;
@@ -755,7 +766,7 @@ void k_wreg(const DecodeArgs a) {
     using Lay = WaveLds<S, L, 0, 0, 1, true>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
     const int g = (threadIdx.x & 63) / G::SEG;
-    const long shot = (long)blockIdx.x * G::SPW + g;
+    const long shot = xcd_wave_index(blockIdx.x, gridDim.x) * G::SPW + g;
     ShotRef ref[1];
     ref[0].shot = shot < a.batch ? shot : -1;
     ref[0].syn = a.syn + (shot < a.batch ? shot : 0) * G::SW;
