@@ -293,7 +293,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     using prior_t = typename Fmt<FMT>::prior_t;
     using acc_t = typename std::conditional<FMT == 0, float, int>::type;
     static_assert(L <= 64 || NG == 1, "L = 128 uses both halves for one shot");
-    static_assert(!REG || (FMT == 0 && SCHED == 0 && !WEIGHTED && L <= 64 && NG == 1),
+    static_assert(!REG || (FMT == 0 && SCHED == 0 && L <= 64 && NG == 1),
                   "register-resident messages: FP32 flooding, L <= 64, one group");
     constexpr bool GRP = L <= 64;                 // halves are independent groups
     constexpr int H = GRP ? NG : L / 64;          // halves per lane
@@ -348,9 +348,13 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     };
 
     bool valid[NG];
+    bool any_valid = false;
 #pragma unroll
-    for (int q = 0; q < NG; ++q)
+    for (int q = 0; q < NG; ++q) {
         valid[q] = ref[q].shot >= 0 && !(a.only && a.only[ref[q].shot] == 0);
+        any_valid = any_valid || valid[q];
+    }
+    if (ballot(any_valid) == 0) return;   // nothing to decode in this wave (masked or past the batch)
 
     // Syndrome bits of this lane's checks: bit R of sb[h] = s of check R*L + p + posoff(h).
     uint32_t sb[H];
@@ -755,12 +759,13 @@ void k_wave(const DecodeArgs a) {
 // staging, so occupancy is set by registers.  With per-shot priors and no
 // posterior output the working set beside the 120 message registers fits
 // three waves per SIMD (168 VGPRs; the only spills are outside the iteration
-// loop); per-bit priors or posteriors need two (256 VGPRs).
-template <bool PER_BIT, bool POST>
+// loop; with per-edge weights a few reloads per iteration, still faster than
+// two waves); per-bit priors or posteriors need two (256 VGPRs).
+template <bool PER_BIT, bool POST, bool WEIGHTED>
 constexpr int reg_waves() { return (!PER_BIT && !POST) ? 3 : 2; }
 
-template <class S, int L, bool PER_BIT, bool POST>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(reg_waves<PER_BIT, POST>())))
+template <class S, int L, bool PER_BIT, bool POST, bool WEIGHTED = false>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(reg_waves<PER_BIT, POST, WEIGHTED>())))
 void k_wreg(const DecodeArgs a) {
     using G = Geo<S, L>;
     using Lay = WaveLds<S, L, 0, 0, 1, true>;
@@ -771,7 +776,16 @@ void k_wreg(const DecodeArgs a) {
     ref[0].shot = shot < a.batch ? shot : -1;
     ref[0].syn = a.syn + (shot < a.batch ? shot : 0) * G::SW;
     ref[0].err = a.err + (shot < a.batch ? shot : 0) * G::EW;
-    wave_decode<S, L, 0, 0, PER_BIT, POST, false, 1, true>(a, a.code, ref, lds);
+    wave_decode<S, L, 0, 0, PER_BIT, POST, WEIGHTED, 1, true>(a, a.code, ref, lds);
+}
+
+// Neural min-sum inference (per-edge weights, per-shot priors, no posterior).
+template <class S, int L>
+hipError_t launch_wreg_weighted(const DecodeArgs &a, hipStream_t st) {
+    using G = Geo<S, L>;
+    const unsigned grid = (unsigned)((a.batch + G::SPW - 1) / G::SPW);
+    hipLaunchKernelGGL((k_wreg<S, L, false, false, true>), dim3(grid), dim3(64), 0, st, a);
+    return hipGetLastError();
 }
 
 template <class S, int L>

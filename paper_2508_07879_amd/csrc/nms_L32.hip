@@ -3,6 +3,8 @@
 
 namespace qldpc {
 
+hipError_t launch_wreg_weighted_L32(const DecodeArgs &a, hipStream_t st);
+
 hipError_t launch_nms_L32(int op, const NmsArgs &n, const DecodeArgs &d, hipStream_t st) {
     using S = ShapeLP35Z;
     using G = Geo<S, 32>;
@@ -18,10 +20,8 @@ hipError_t launch_nms_L32(int op, const NmsArgs &n, const DecodeArgs &d, hipStre
             hipLaunchKernelGGL((k_nms_reduce<S, 32>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n);
             break;
         }
-        case 3:
-            hipLaunchKernelGGL((k_wave<S, 32, 0, 0, false, false, true>),
-                               dim3((unsigned)((d.batch + G::SPW - 1) / G::SPW)), dim3(64), 0, st, d);
-            break;
+        case 3:   // inference: messages in registers
+            return launch_wreg_weighted_L32(d, st);
         default:
             return hipErrorNotSupported;
     }

@@ -8,4 +8,8 @@ hipError_t launch_wreg_L64(const LaunchKey &k, const DecodeArgs &a, hipStream_t 
     return launch_wreg<ShapeLP35Z, 64>(k, a, st);
 }
 
+hipError_t launch_wreg_weighted_L64(const DecodeArgs &a, hipStream_t st) {
+    return launch_wreg_weighted<ShapeLP35Z, 64>(a, st);
+}
+
 }  // namespace qldpc

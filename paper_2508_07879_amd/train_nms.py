@@ -58,12 +58,13 @@ def main(argv=None):
     ap.add_argument("--eval-seed", type=int, default=2_000_003)
     ap.add_argument("--out", default="")
     ap.add_argument("--json", default="")
+    ap.add_argument("--load", default="", help="evaluate these saved weights instead of training")
     args = ap.parse_args(argv)
 
     import torch
 
-    from paper_2508_07879_amd import Decoder, abi, nms
-    from workload import bits, gf2, lp
+    from paper_2508_07879_amd import Decoder, nms
+    from workload import lp
 
     dev = torch.device("cuda", 0)
     code = lp.lp_code(args.L)
@@ -73,6 +74,24 @@ def main(argv=None):
     report = dict(L=args.L, n=side.n, p=args.p, T=T, batch=args.batch, lr=args.lr, epochs=args.epochs,
                   train_shots=args.train_shots, eval_shots=args.eval_shots)
 
+    if args.load:
+        w, meta, _ = nms.load_weights(args.load, side)
+        w = w.to(dev)
+        T = int(w.shape[0])
+        report.update(T=T, loaded=args.load, trained=meta)
+        print(f"loaded weights [{T}][{side.nnz}] from {args.load}", flush=True)
+    else:
+        w = _train(args, dec, side, dev, report)
+    return _evaluate(args, code, side, dec, dev, w, T, report)
+
+
+def _train(args, dec, side, dev, report):
+    import torch
+
+    from paper_2508_07879_amd import nms
+    from workload import bits
+
+    T = args.T
     # ---- training data, resident on the device -----------------------------
     t0 = time.time()
     syn_all, pr_all, e_all = [], [], []
@@ -109,6 +128,14 @@ def main(argv=None):
     if args.out:
         nms.save_weights(args.out, w, side, meta=report, optimizer=opt)
     del syn_all, pr_all, e_all
+    return w
+
+
+def _evaluate(args, code, side, dec, dev, w, T, report):
+    import torch
+
+    from paper_2508_07879_amd import abi, nms
+    from workload import bits, gf2
 
     # ---- evaluation on held-out shots ---------------------------------------
     lam = gf2.logical_basis(code.hx.dense(), side.dense())
@@ -134,10 +161,10 @@ def main(argv=None):
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ev0.record()
             if kind == "nms":
-                fbp = dec.params(max_iters=32, layout=abi.QLDPC_LAYOUT_WAVE) if fb else None
+                fbp = dec.params(max_iters=32) if fb else None
                 abi.qldpc_nbp_decode(dec.handle, B, t, wd[:t].contiguous(), fbp, syn, pr, err, conv, it, used)
             else:
-                prm = dec.params(max_iters=t, layout=abi.QLDPC_LAYOUT_WAVE)
+                prm = dec.params(max_iters=t)
                 abi.qldpc_decode_batch(dec.handle, prm, B, syn, pr, err, conv, it, None)
             ev1.record()
             torch.cuda.synchronize()
