@@ -246,9 +246,11 @@ qldpc_status qldpc_session_latency(qldpc_session s, int32_t nreq, int32_t batch,
 
 /* ------------------------------------------------------------------------ */
 /* Mixed-code persistent batches: shots of several lifted codes (L in        */
-/* {16, 32, 64, 128}, H_Z pattern) with per-shot priors decoded in one       */
-/* persistent launch (batching of many decoders, Table 1 "asynchronous      */
-/* kernel execution"; each shot follows Algorithm 1 on its own code).       */
+/* {16, 32, 64, 128}, H_Z or H_X pattern) with per-shot priors decoded in    */
+/* one persistent launch sequence (batching of many decoders, Table 1       */
+/* "asynchronous kernel execution"; each shot follows Algorithm 1 on its    */
+/* own code).  Both sides of a CSS code can share one batch, the paper's    */
+/* concatenated X and Z decoding (Section 2).                               */
 /* ------------------------------------------------------------------------ */
 
 typedef struct qldpc_mixed_s *qldpc_mixed;
@@ -336,7 +338,8 @@ qldpc_status qldpc_nbp_decode(qldpc_code code, int32_t batch, int32_t T, const f
 typedef struct qldpc_server_s *qldpc_server;
 
 typedef struct {
-    const qldpc_code *codes;          /* 1..8 codes served (H_Z pattern)            */
+    const qldpc_code *codes;          /* 1..8 codes served (H_Z or H_X pattern;
+                                         neural weights for H_Z ones only)          */
     int32_t ncodes;
     const float *const *nms_weights;  /* per code: device [nms_T][nnz] neural weights
                                          or NULL (plain min-sum only); the array may

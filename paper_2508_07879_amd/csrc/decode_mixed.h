@@ -5,11 +5,13 @@
 //
 // Shots are bucketed by code on the device (counting pass, then a scatter
 // into a code-ordered index list, largest L first).  One persistent grid of
-// wavefronts per lift size L then claims tiles of same-code shots from its
-// own atomic counter until none are left: for L <= 64 every message stays in
-// registers (one 64-lane group of 64 / L shots per tile, three waves per
-// SIMD), for L = 128 in LDS (one shot per tile).  Each shot's result depends
-// only on its own syndrome and prior, never on its tile mates or grid.
+// wavefronts per (block pattern, lift size) then claims tiles of same-code
+// shots from its own atomic counter until none are left: for L <= 64 every
+// message stays in registers (one 64-lane group of 64 / L shots per tile),
+// for L = 128 in LDS (one shot per tile).  Codes of both patterns (H_Z and
+// H_X of one CSS code, say) can share a batch, so both sides of a code are
+// decoded in one launch sequence.  Each shot's result depends only on its
+// own syndrome and prior, never on its tile mates or grid.
 #pragma once
 #include "decode_wave.h"
 
@@ -21,6 +23,7 @@ struct MixedArgs {
     DecodeArgs base;                       // alpha, iterations, priors, conv / iters outputs
     const DevCode *codes[kMaxMixCodes];
     int32_t L[kMaxMixCodes];
+    int32_t which[kMaxMixCodes];           // block pattern: 0 = H_Z, 1 = H_X
     int32_t rank[kMaxMixCodes];            // bucket order of each code (largest L first)
     int32_t ncodes;
     const int32_t *shot_code;              // [batch]
@@ -28,7 +31,7 @@ struct MixedArgs {
     const int64_t *err_off;                // [batch], words into err
     const uint32_t *syn;
     uint32_t *err;
-    int32_t *scratch;                      // counts[8], cursors[8], tile counters[4], order[batch]
+    int32_t *scratch;                      // counts[8], cursors[8], tile counters[8], order[batch]
     int32_t batch;
 };
 
@@ -36,11 +39,15 @@ namespace mix {
 
 __device__ __forceinline__ int32_t *counts(const MixedArgs &m) { return m.scratch; }
 __device__ __forceinline__ int32_t *cursors(const MixedArgs &m) { return m.scratch + kMaxMixCodes; }
-constexpr int kMixGrids = 4;   // one persistent grid per lift size: 16, 32, 64, 128
+constexpr int kMixGrids = 8;   // one persistent grid per (pattern, lift size 16 / 32 / 64 / 128)
 constexpr int kScratchHead = 2 * kMaxMixCodes + kMixGrids;
 
-__host__ __device__ __forceinline__ int grid_of(int L) { return L == 16 ? 0 : L == 32 ? 1 : L == 64 ? 2 : 3; }
-__device__ __forceinline__ int32_t *tile_ctr(const MixedArgs &m, int L) { return m.scratch + 2 * kMaxMixCodes + grid_of(L); }
+__host__ __device__ __forceinline__ int grid_of(int which, int L) {
+    return 4 * which + (L == 16 ? 0 : L == 32 ? 1 : L == 64 ? 2 : 3);
+}
+__device__ __forceinline__ int32_t *tile_ctr(const MixedArgs &m, int which, int L) {
+    return m.scratch + 2 * kMaxMixCodes + grid_of(which, L);
+}
 __device__ __forceinline__ int32_t *order(const MixedArgs &m) { return m.scratch + kScratchHead; }
 __host__ __device__ constexpr int shots_per_tile(int L) { return L <= 64 ? 64 / L : 1; }
 
@@ -89,7 +96,7 @@ __device__ __forceinline__ void mix_tile(const MixedArgs &m, int c, int first, i
     wave_decode<S, L, 0, 0, false, false, false, 1, REG>(m.base, m.codes[c], ref, lds);
 }
 
-// Persistent decoder of the shots whose code has lift size L.  A claimed
+// Persistent decoder of the shots whose code has pattern S and lift size L.  A claimed
 // tile is located by a short scalar walk over the codes in bucket order, so
 // nothing but pointers stays live across tiles (the decoder body needs the
 // registers).  Waves per SIMD: three for L <= 32; two for L = 64, whose
@@ -102,7 +109,7 @@ void k_mix_decode(const MixedArgs m) {
     constexpr int spt = mix::shots_per_tile(L);
     for (;;) {
         int t = 0;
-        if ((threadIdx.x & 63) == 0) t = atomicAdd(mix::tile_ctr(m, L), 1);
+        if ((threadIdx.x & 63) == 0) t = atomicAdd(mix::tile_ctr(m, S::WHICH, L), 1);
         t = __builtin_amdgcn_readfirstlane(t);
         int c = -1, first = 0, cnt = 0;
         for (int r = 0, acc = 0, tiles = 0; r < m.ncodes; ++r) {
@@ -110,7 +117,7 @@ void k_mix_decode(const MixedArgs m) {
             for (int d = 0; d < m.ncodes; ++d)
                 if (m.rank[d] == r) cc = d;
             const int n = __builtin_amdgcn_readfirstlane(mix::counts(m)[cc]);
-            if (m.L[cc] == L) {
+            if (m.L[cc] == L && m.which[cc] == S::WHICH) {
                 const int nt = (n + spt - 1) / spt;
                 if (c < 0 && t < tiles + nt) {
                     c = cc;
@@ -121,7 +128,7 @@ void k_mix_decode(const MixedArgs m) {
             }
             acc += n;
         }
-        if (c < 0) return;   // every tile of this lift size is taken
+        if (c < 0) return;   // every tile of this pattern and lift size is taken
         mix_tile<S, L>(m, c, first, cnt, lds);
     }
 }

@@ -18,7 +18,7 @@ struct qldpc_mixed_s {
     qldpc_decode_params params{};
     int32_t waves = 0;              // persistent grid size for each lift L <= 64 (registers)
     int32_t waves128 = 0;           // and for L = 128 (LDS)
-    bool has_L[mix::kMixGrids] = {};
+    bool has_grid[mix::kMixGrids] = {};   // (pattern, L) pairs among the plan's codes
     int32_t *scratch = nullptr;     // device
     std::mutex mu;
     std::map<std::tuple<int32_t, const void *, const void *, const void *, const void *, const void *, const void *,
@@ -44,6 +44,7 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
     for (int c = 0; c < x->ncodes; ++c) {
         m.codes[c] = x->codes[c]->dev;
         m.L[c] = x->codes[c]->L;
+        m.which[c] = x->codes[c]->which;
     }
     // bucket order: largest L first, then code index
     for (int c = 0; c < x->ncodes; ++c) {
@@ -63,11 +64,17 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
     hipLaunchKernelGGL(k_mix_clear, dim3(1), dim3(64), 0, st, m);
     hipLaunchKernelGGL(k_mix_count, dim3(nb), dim3(256), 0, st, m);
     hipLaunchKernelGGL(k_mix_scatter, dim3(nb), dim3(256), 0, st, m);
-    // one persistent grid per lift size present, largest L first (bucket order)
-    if (x->has_L[3]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 128>), dim3((unsigned)x->waves128), dim3(64), 0, st, m);
-    if (x->has_L[2]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 64>), dim3((unsigned)waves), dim3(64), 0, st, m);
-    if (x->has_L[1]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 32>), dim3((unsigned)waves), dim3(64), 0, st, m);
-    if (x->has_L[0]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 16>), dim3((unsigned)waves), dim3(64), 0, st, m);
+    // one persistent grid per (pattern, lift size) present, largest L first
+    const unsigned w64 = (unsigned)waves, w128 = (unsigned)x->waves128;
+    const bool *g = x->has_grid;
+    if (g[3]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 128>), dim3(w128), dim3(64), 0, st, m);
+    if (g[7]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 128>), dim3(w128), dim3(64), 0, st, m);
+    if (g[2]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 64>), dim3(w64), dim3(64), 0, st, m);
+    if (g[6]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 64>), dim3(w64), dim3(64), 0, st, m);
+    if (g[1]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 32>), dim3(w64), dim3(64), 0, st, m);
+    if (g[5]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 32>), dim3(w64), dim3(64), 0, st, m);
+    if (g[0]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 16>), dim3(w64), dim3(64), 0, st, m);
+    if (g[4]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 16>), dim3(w64), dim3(64), 0, st, m);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "mixed_decode: launch");
     return QLDPC_OK;
@@ -88,7 +95,6 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
         return set_error(QLDPC_ERR_INVALID_ARG, "mixed_create: bad iterations or alpha");
     for (int c = 0; c < ncodes; ++c) {
         if (!codes[c]) return set_error(QLDPC_ERR_INVALID_ARG, "mixed_create: null code");
-        if (codes[c]->which != 0) return set_error(QLDPC_ERR_UNSUPPORTED, "mixed_create: H_Z patterns only");
         if (codes[c]->device != codes[0]->device) return set_error(QLDPC_ERR_INVALID_ARG, "mixed_create: codes on different devices");
     }
     auto *x = new (std::nothrow) qldpc_mixed_s();
@@ -109,7 +115,7 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
             delete x;
             return set_error(QLDPC_ERR_UNSUPPORTED, "mixed_create: lifts 16, 32, 64 and 128 only");
         }
-        x->has_L[mix::grid_of(L)] = true;
+        x->has_grid[mix::grid_of(codes[c]->which, L)] = true;
     }
     hipError_t e = hipSetDevice(x->device);
     if (e == hipSuccess) e = hipMalloc(&x->scratch, sizeof(int32_t) * (mix::kScratchHead + (size_t)max_batch));

@@ -290,6 +290,11 @@ qldpc_status qldpc_server_create(const qldpc_server_config *cfg, qldpc_server *o
         return set_error(QLDPC_ERR_INVALID_ARG, "server_create: sizes must be positive");
     if (cfg->nms_weights && (cfg->nms_T < 1 || cfg->nms_T > 255))
         return set_error(QLDPC_ERR_INVALID_ARG, "server_create: nms_T must be in [1, 255]");
+    for (int c = 0; c < cfg->ncodes; ++c) {
+        if (!cfg->codes[c]) return set_error(QLDPC_ERR_INVALID_ARG, "server_create: null code");
+        if (cfg->nms_weights && cfg->nms_weights[c] && cfg->codes[c]->which != 0)
+            return set_error(QLDPC_ERR_UNSUPPORTED, "server_create: neural weights for H_Z-pattern codes only");
+    }
     auto *srv = new (std::nothrow) qldpc_server_s();
     if (!srv) return set_error(QLDPC_ERR_OUT_OF_MEMORY, "server_create: host allocation");
     srv->cfg = *cfg;

@@ -4,8 +4,9 @@
 namespace qldpc {
 
 hipError_t launch_wreg_L16(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
-    if (k.which != 0) return hipErrorNotSupported;
-    return launch_wreg<ShapeLP35Z, 16>(k, a, st);
+    if (k.which == 0) return launch_wreg<ShapeLP35Z, 16>(k, a, st);
+    if (k.which == 1) return launch_wreg<ShapeLP35X, 16>(k, a, st);
+    return hipErrorNotSupported;
 }
 
 }  // namespace qldpc

@@ -4,8 +4,9 @@
 namespace qldpc {
 
 hipError_t launch_wreg_L32(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
-    if (k.which != 0) return hipErrorNotSupported;
-    return launch_wreg<ShapeLP35Z, 32>(k, a, st);
+    if (k.which == 0) return launch_wreg<ShapeLP35Z, 32>(k, a, st);
+    if (k.which == 1) return launch_wreg<ShapeLP35X, 32>(k, a, st);
+    return hipErrorNotSupported;
 }
 
 hipError_t launch_wreg_weighted_L32(const DecodeArgs &a, hipStream_t st) {

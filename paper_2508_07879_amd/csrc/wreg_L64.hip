@@ -4,8 +4,9 @@
 namespace qldpc {
 
 hipError_t launch_wreg_L64(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
-    if (k.which != 0) return hipErrorNotSupported;
-    return launch_wreg<ShapeLP35Z, 64>(k, a, st);
+    if (k.which == 0) return launch_wreg<ShapeLP35Z, 64>(k, a, st);
+    if (k.which == 1) return launch_wreg<ShapeLP35X, 64>(k, a, st);
+    return hipErrorNotSupported;
 }
 
 hipError_t launch_wreg_weighted_L64(const DecodeArgs &a, hipStream_t st) {
