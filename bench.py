@@ -178,9 +178,11 @@ def main():
     # ---------------- other formats and schedules ----------------------------
     variants = {}
     if not args.no_variants:
-        for name, fmt, sched, bpm in (("f32_flood_lds_layout", 0, 0, 4), ("int8_flood", 1, 0, 1),
-                                      ("f32_layered", 0, 1, 4), ("int8_layered", 1, 1, 1)):
-            w, k_, it_ = measure(fmt, sched, max(3, args.steps // 4), 1)
+        W, RG = abi.QLDPC_LAYOUT_WAVE, abi.QLDPC_LAYOUT_WAVE_REG
+        for name, fmt, sched, bpm, lay in (("f32_flood_lds_layout", 0, 0, 4, W), ("int8_flood", 1, 0, 1, W),
+                                           ("f32_layered", 0, 1, 4, RG if args.L <= 64 else W),
+                                           ("f32_layered_lds_layout", 0, 1, 4, W), ("int8_layered", 1, 1, 1, W)):
+            w, k_, it_ = measure(fmt, sched, max(3, args.steps // 4), 1, layout=lay)
             st = max(3, args.steps // 4)
             variants[name] = dict(
                 value=syn_per_step * st / w, unit="syndromes/s", ms_per_step=w * 1e3 / st,

@@ -125,10 +125,11 @@ typedef enum {
                                 shots when L < 64); throughput layout        */
     QLDPC_LAYOUT_BLOCK = 2,  /* one workgroup of several wavefronts decodes
                                 one shot; latency layout                     */
-    QLDPC_LAYOUT_WAVE_REG = 3 /* as WAVE, with every message kept in the
-                                lanes' registers and moved between lanes by
-                                cross-lane permutes instead of LDS; FP32
-                                flooding with L <= 64 only (otherwise
+    QLDPC_LAYOUT_WAVE_REG = 3 /* as WAVE, with every message (and, layered,
+                                every a-posteriori value) kept in the lanes'
+                                registers and moved between lanes by
+                                cross-lane permutes instead of LDS; FP32 with
+                                L <= 64 only (otherwise
                                 QLDPC_ERR_UNSUPPORTED)                       */
 } qldpc_layout;
 

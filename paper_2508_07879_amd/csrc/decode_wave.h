@@ -91,7 +91,7 @@ struct WaveLds {
     static constexpr int H = L <= 64 ? NG : L / 64;
     static constexpr int ROW = 64 * H;
     static constexpr int MSG = REG ? 0 : S::SLOTS * ROW;
-    static constexpr int QN = SCHED == 1 ? S::NB * ROW : 0;
+    static constexpr int QN = (SCHED == 1 && !REG) ? S::NB * ROW : 0;
     static constexpr size_t msg_bytes = MSG * sizeof(msg_t);
     static constexpr size_t q_off = (msg_bytes + 15) & ~size_t(15);
     static constexpr size_t e_off = (q_off + QN * sizeof(q_t) + 15) & ~size_t(15);
@@ -274,13 +274,17 @@ struct ShotRef {
 // each decoding its own 64 / L shots (ref[h] describes group h's segment of
 // this lane).  `lds` points to WaveLds<S, L, FMT, SCHED, NG, REG>::bytes.
 //
-// REG (FP32 flooding, L <= 64, one group): the lane's entry of every slot
-// row is kept in a register array m[slot] instead of LDS.  The check pass
-// then works on registers only; the variable pass fetches the entry a
-// variable reaches through a block of shift s from lane (t - s) mod L with a
+// REG (FP32, L <= 64, one group): the lane's entry of every slot row is
+// kept in a register array m[slot] instead of LDS.  Flooding: the check pass
+// works on registers only; the variable pass fetches the entry a variable
+// reaches through a block of shift s from lane (t - s) mod L with a
 // cross-lane permute (ds_bpermute) and returns its new message to lane
-// (t + s) mod L the same way.  Values and the order of every operation are
-// those of the LDS form; only where the messages are kept differs.
+// (t + s) mod L the same way.  Layered: the check messages r never move;
+// the lane's a-posteriori values Q of all 34 block columns are registers
+// too, and each layer fetches the Q its check sees through shift s from lane
+// (t + s) mod L and returns the updated Q to lane (t - s) mod L.  Values and
+// the order of every operation are those of the LDS form; only where the
+// messages are kept differs.
 // ---------------------------------------------------------------------------
 template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED, int NG, bool REG = false>
 __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *__restrict__ code,
@@ -293,8 +297,8 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     using prior_t = typename Fmt<FMT>::prior_t;
     using acc_t = typename std::conditional<FMT == 0, float, int>::type;
     static_assert(L <= 64 || NG == 1, "L = 128 uses both halves for one shot");
-    static_assert(!REG || (FMT == 0 && SCHED == 0 && L <= 64 && NG == 1),
-                  "register-resident messages: FP32 flooding, L <= 64, one group");
+    static_assert(!REG || (FMT == 0 && L <= 64 && NG == 1 && !(WEIGHTED && SCHED == 1)),
+                  "register-resident messages: FP32, L <= 64, one group");
     constexpr bool GRP = L <= 64;                 // halves are independent groups
     constexpr int H = GRP ? NG : L / 64;          // halves per lane
     constexpr int MB = S::MB, NB = S::NB, DC = S::DC, ROW = 64 * H;
@@ -325,6 +329,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     // hits) instead of hoisting all 120 out of the loop into scalar registers
     // it does not have.
     float m[REG ? S::SLOTS : 1];
+    float Qv[(REG && SCHED == 1) ? S::NB : 1];   // layered: this lane's Q of every block column
     const uint32_t lane4 = (uint32_t)lane << 2;
     CodePtr cpb = const_code(code);
     auto reload_table = [&]() {
@@ -412,6 +417,9 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                 }
             });
         });
+    } else if constexpr (REG) {
+        static_for<0, S::SLOTS>([&](auto Sc) { m[decltype(Sc)::value] = 0.0f; });
+        static_for<0, NB>([&](auto Cc) { Qv[decltype(Cc)::value] = gamma_of(decltype(Cc)::value, 0); });
     } else {
 #pragma unroll
         for (int sl = 0; sl < S::SLOTS; ++sl)
@@ -480,6 +488,27 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
             // ---------------- layers: one block row at a time ----------------
             static_for<0, MB>([&](auto Rc) {
                 constexpr int R = decltype(Rc)::value;
+                if constexpr (REG) {
+                    reload_table();
+                    const uint32_t P = sb[0] << (31 - R);
+                    float v[DC], c[DC];
+                    static_for<0, DC>([&](auto Jc) {
+                        constexpr int j = decltype(Jc)::value;
+                        constexpr int C = S::T.slot_bc[R][j];
+                        // Q of the variable (C, t + s) this lane's check sees, minus the old r
+                        v[j] = bperm(cn_src(shift_of(R * DC + j)), Qv[C]) - m[R * DC + j];
+                        c[j] = v[j];
+                    });
+                    cn_f32<DC>(c, P, a.alpha);
+                    static_for<0, DC>([&](auto Jc) {
+                        constexpr int j = decltype(Jc)::value;
+                        constexpr int C = S::T.slot_bc[R][j];
+                        m[R * DC + j] = c[j];
+                        // the variable at position t receives the value of check t - s
+                        Qv[C] = bperm(vn_src(shift_of(R * DC + j)), v[j] + c[j]);
+                    });
+                    return;
+                }
 #pragma unroll
                 for (int h = 0; h < H; ++h) {
                     const uint32_t P = sb[h] << (31 - R);
@@ -599,6 +628,8 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                             for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
                             Q = sum;
                         }
+                    } else if constexpr (REG) {
+                        Q = Qv[C];
                     } else {
                         Q = (acc_t)Qs[C * ROW + lane + 64 * h];
                     }
@@ -761,14 +792,14 @@ void k_wave(const DecodeArgs a) {
 // three waves per SIMD (168 VGPRs; the only spills are outside the iteration
 // loop; with per-edge weights a few reloads per iteration, still faster than
 // two waves); per-bit priors or posteriors need two (256 VGPRs).
-template <bool PER_BIT, bool POST, bool WEIGHTED>
+template <bool PER_BIT, bool POST, bool WEIGHTED, int SCHED = 0>
 constexpr int reg_waves() { return (!PER_BIT && !POST) ? 3 : 2; }
 
-template <class S, int L, bool PER_BIT, bool POST, bool WEIGHTED = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(reg_waves<PER_BIT, POST, WEIGHTED>())))
+template <class S, int L, bool PER_BIT, bool POST, bool WEIGHTED = false, int SCHED = 0>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(reg_waves<PER_BIT, POST, WEIGHTED, SCHED>())))
 void k_wreg(const DecodeArgs a) {
     using G = Geo<S, L>;
-    using Lay = WaveLds<S, L, 0, 0, 1, true>;
+    using Lay = WaveLds<S, L, 0, SCHED, 1, true>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
     const int g = (threadIdx.x & 63) / G::SEG;
     const long shot = xcd_wave_index(blockIdx.x, gridDim.x) * G::SPW + g;
@@ -776,7 +807,7 @@ void k_wreg(const DecodeArgs a) {
     ref[0].shot = shot < a.batch ? shot : -1;
     ref[0].syn = a.syn + (shot < a.batch ? shot : 0) * G::SW;
     ref[0].err = a.err + (shot < a.batch ? shot : 0) * G::EW;
-    wave_decode<S, L, 0, 0, PER_BIT, POST, WEIGHTED, 1, true>(a, a.code, ref, lds);
+    wave_decode<S, L, 0, SCHED, PER_BIT, POST, WEIGHTED, 1, true>(a, a.code, ref, lds);
 }
 
 // Neural min-sum inference (per-edge weights, per-shot priors, no posterior).
@@ -788,18 +819,25 @@ hipError_t launch_wreg_weighted(const DecodeArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <class S, int L, int SCHED>
+void launch_wreg_sched(const LaunchKey &k, const DecodeArgs &a, unsigned grid, hipStream_t st) {
+    if (k.per_bit) {
+        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, true, true, false, SCHED>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_wreg<S, L, true, false, false, SCHED>), dim3(grid), dim3(64), 0, st, a);
+    } else {
+        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, false, true, false, SCHED>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_wreg<S, L, false, false, false, SCHED>), dim3(grid), dim3(64), 0, st, a);
+    }
+}
+
 template <class S, int L>
 hipError_t launch_wreg(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
-    if (k.fmt != 0 || k.sched != 0) return hipErrorNotSupported;
+    if (k.fmt != 0) return hipErrorNotSupported;
     using G = Geo<S, L>;
     const unsigned grid = (unsigned)((a.batch + G::SPW - 1) / G::SPW);
-    if (k.per_bit) {
-        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, true, true>), dim3(grid), dim3(64), 0, st, a);
-        else hipLaunchKernelGGL((k_wreg<S, L, true, false>), dim3(grid), dim3(64), 0, st, a);
-    } else {
-        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, false, true>), dim3(grid), dim3(64), 0, st, a);
-        else hipLaunchKernelGGL((k_wreg<S, L, false, false>), dim3(grid), dim3(64), 0, st, a);
-    }
+    if (k.sched == 0) launch_wreg_sched<S, L, 0>(k, a, grid, st);
+    else if (k.sched == 1) launch_wreg_sched<S, L, 1>(k, a, grid, st);
+    else return hipErrorNotSupported;
     return hipGetLastError();
 }
 

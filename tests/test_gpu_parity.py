@@ -174,8 +174,17 @@ def test_register_resident_edge_cases():
     assert np.all(g[1] == 1) and np.all(g[2] == 1)
 
 
+@pytest.mark.parametrize("L", [16, 32, 64])
+@pytest.mark.parametrize("per_bit", [False, True])
+def test_register_resident_layered(L, per_bit):
+    """Layered schedule with check messages and a-posteriori values in
+    registers: identical to the oracle's layered decoder (layer = block row)."""
+    run_case(L, 300 if L < 64 else 130, 0.05, sched=1, per_bit=per_bit, seed=27, layout=REG)
+    run_case(L, 100, 0.03, sched=1, per_bit=per_bit, max_iters=7, early_stop=False, seed=28, layout=REG)
+
+
 def test_register_resident_rejects_unsupported():
-    for L, fmt, sched in ((64, 1, 0), (64, 0, 1), (128, 0, 0)):
+    for L, fmt, sched in ((64, 1, 0), (64, 1, 1), (128, 0, 0), (128, 0, 1)):
         c, H, dec = code(L)
         p = dec.params(fmt=fmt, sched=sched, layout=REG)
         err, conv, it, _ = dec.outputs(2)
@@ -188,7 +197,7 @@ def test_register_resident_rejects_unsupported():
 
 @pytest.mark.parametrize("fmt,sched,layout", [(0, 0, abi.QLDPC_LAYOUT_WAVE), (1, 0, abi.QLDPC_LAYOUT_WAVE),
                                               (0, 1, abi.QLDPC_LAYOUT_WAVE), (1, 1, abi.QLDPC_LAYOUT_WAVE),
-                                              (0, 0, abi.QLDPC_LAYOUT_WAVE_REG)])
+                                              (0, 0, abi.QLDPC_LAYOUT_WAVE_REG), (0, 1, abi.QLDPC_LAYOUT_WAVE_REG)])
 def test_full_batch_sampled(fmt, sched, layout):
     """65536 shots at L = 64, p = 0.05, as the benchmark launches them; the
     oracle re-decodes a sample of shots one by one, and every converged shot
