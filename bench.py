@@ -179,9 +179,10 @@ def main():
     variants = {}
     if not args.no_variants:
         W, RG = abi.QLDPC_LAYOUT_WAVE, abi.QLDPC_LAYOUT_WAVE_REG
-        for name, fmt, sched, bpm, lay in (("f32_flood_lds_layout", 0, 0, 4, W), ("int8_flood", 1, 0, 1, W),
-                                           ("f32_layered", 0, 1, 4, RG if args.L <= 64 else W),
-                                           ("f32_layered_lds_layout", 0, 1, 4, W), ("int8_layered", 1, 1, 1, W)):
+        R_ = RG if args.L <= 64 else W
+        for name, fmt, sched, bpm, lay in (("f32_flood_lds_layout", 0, 0, 4, W), ("int8_flood", 1, 0, 1, R_),
+                                           ("f32_layered", 0, 1, 4, R_), ("f32_layered_lds_layout", 0, 1, 4, W),
+                                           ("int8_layered", 1, 1, 1, R_)):
             w, k_, it_ = measure(fmt, sched, max(3, args.steps // 4), 1, layout=lay)
             st = max(3, args.steps // 4)
             variants[name] = dict(

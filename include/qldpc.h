@@ -128,9 +128,9 @@ typedef enum {
     QLDPC_LAYOUT_WAVE_REG = 3 /* as WAVE, with every message (and, layered,
                                 every a-posteriori value) kept in the lanes'
                                 registers and moved between lanes by
-                                cross-lane permutes instead of LDS; FP32 with
-                                L <= 64 only (otherwise
-                                QLDPC_ERR_UNSUPPORTED)                       */
+                                cross-lane permutes instead of LDS (int8
+                                messages as 32-bit integers); L <= 64 only
+                                (otherwise QLDPC_ERR_UNSUPPORTED)            */
 } qldpc_layout;
 
 typedef struct {

@@ -94,7 +94,7 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
                 found = true;
             }
         }
-        const bool reg_ok = p->fmt == QLDPC_F32 && code->L <= 64;
+        const bool reg_ok = code->L <= 64;
         if (!found)
             layout = (block_ok && batch < 512) ? QLDPC_LAYOUT_BLOCK
                      : reg_ok                  ? QLDPC_LAYOUT_WAVE_REG
@@ -105,8 +105,8 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
             return fail(QLDPC_ERR_UNSUPPORTED, "decode: the workgroup layout needs flooding and L >= 64");
         if (nw == 0) nw = 16;
     }
-    if (layout == QLDPC_LAYOUT_WAVE_REG && !(p->fmt == QLDPC_F32 && code->L <= 64))
-        return fail(QLDPC_ERR_UNSUPPORTED, "decode: register-resident messages need FP32 and L <= 64");
+    if (layout == QLDPC_LAYOUT_WAVE_REG && code->L > 64)
+        return fail(QLDPC_ERR_UNSUPPORTED, "decode: register-resident messages need L <= 64");
     key->layout = layout;
     key->nw = nw;
     return QLDPC_OK;
@@ -303,7 +303,7 @@ qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, 
     if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, "autotune: null buffer");
     struct Cand { int layout, nw; };
     std::vector<Cand> cands = {{QLDPC_LAYOUT_WAVE, 0}};
-    if (params->fmt == QLDPC_F32 && code->L <= 64) cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});
+    if (code->L <= 64) cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});
     if (params->sched == QLDPC_FLOOD && code->L >= 64) {
         cands.push_back({QLDPC_LAYOUT_BLOCK, 8});
         cands.push_back({QLDPC_LAYOUT_BLOCK, 16});
@@ -397,9 +397,8 @@ qldpc_status qldpc_tune_load(qldpc_code code, const char *path) {
         const int layout = (int)nums[i + 1], nw = (int)nums[i + 2];
         if (layout != QLDPC_LAYOUT_WAVE && layout != QLDPC_LAYOUT_BLOCK && layout != QLDPC_LAYOUT_WAVE_REG) continue;
         if (layout == QLDPC_LAYOUT_BLOCK && nw != 8 && nw != 16) continue;
-        const int key = (int)nums[i], fmt = key / 32, sched = (key / 16) % 2;   // see tune_key
-        if (layout == QLDPC_LAYOUT_WAVE_REG && !(fmt == QLDPC_F32 && code->L <= 64)) continue;
-        (void)sched;
+        const int key = (int)nums[i];
+        if (layout == QLDPC_LAYOUT_WAVE_REG && code->L > 64) continue;
         code->tune[key] = TuneChoice{layout, nw, (float)nums[i + 3]};
     }
     return QLDPC_OK;

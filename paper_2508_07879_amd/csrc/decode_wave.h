@@ -216,6 +216,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 __device__ __forceinline__ float bperm(int addr, float v) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
+__device__ __forceinline__ int bperm(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
 
 }  // namespace wave
 
@@ -274,8 +275,8 @@ struct ShotRef {
 // each decoding its own 64 / L shots (ref[h] describes group h's segment of
 // this lane).  `lds` points to WaveLds<S, L, FMT, SCHED, NG, REG>::bytes.
 //
-// REG (FP32, L <= 64, one group): the lane's entry of every slot row is
-// kept in a register array m[slot] instead of LDS.  Flooding: the check pass
+// REG (L <= 64, one group): the lane's entry of every slot row is kept in a
+// register array m[slot] instead of LDS (int8 messages as 32-bit integers).  Flooding: the check pass
 // works on registers only; the variable pass fetches the entry a variable
 // reaches through a block of shift s from lane (t - s) mod L with a
 // cross-lane permute (ds_bpermute) and returns its new message to lane
@@ -297,8 +298,8 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     using prior_t = typename Fmt<FMT>::prior_t;
     using acc_t = typename std::conditional<FMT == 0, float, int>::type;
     static_assert(L <= 64 || NG == 1, "L = 128 uses both halves for one shot");
-    static_assert(!REG || (FMT == 0 && L <= 64 && NG == 1 && !(WEIGHTED && SCHED == 1)),
-                  "register-resident messages: FP32, L <= 64, one group");
+    static_assert(!REG || (L <= 64 && NG == 1 && !(WEIGHTED && (SCHED == 1 || FMT == 1))),
+                  "register-resident messages: L <= 64, one group");
     constexpr bool GRP = L <= 64;                 // halves are independent groups
     constexpr int H = GRP ? NG : L / 64;          // halves per lane
     constexpr int MB = S::MB, NB = S::NB, DC = S::DC, ROW = 64 * H;
@@ -328,8 +329,8 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     // columns, so the compiler reloads each batch's shifts (scalar-cache
     // hits) instead of hoisting all 120 out of the loop into scalar registers
     // it does not have.
-    float m[REG ? S::SLOTS : 1];
-    float Qv[(REG && SCHED == 1) ? S::NB : 1];   // layered: this lane's Q of every block column
+    acc_t m[REG ? S::SLOTS : 1];
+    acc_t Qv[(REG && SCHED == 1) ? S::NB : 1];   // layered: this lane's Q of every block column
     const uint32_t lane4 = (uint32_t)lane << 2;
     CodePtr cpb = const_code(code);
     auto reload_table = [&]() {
@@ -418,7 +419,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
             });
         });
     } else if constexpr (REG) {
-        static_for<0, S::SLOTS>([&](auto Sc) { m[decltype(Sc)::value] = 0.0f; });
+        static_for<0, S::SLOTS>([&](auto Sc) { m[decltype(Sc)::value] = (acc_t)0; });
         static_for<0, NB>([&](auto Cc) { Qv[decltype(Cc)::value] = gamma_of(decltype(Cc)::value, 0); });
     } else {
 #pragma unroll
@@ -474,11 +475,14 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                     } else {
                         int v[DC];
 #pragma unroll
-                        for (int j = 0; j < DC; ++j) v[j] = msg[(R * DC + j) * ROW + lane + 64 * h];
+                        for (int j = 0; j < DC; ++j)
+                            v[j] = REG ? (int)m[R * DC + j] : (int)msg[(R * DC + j) * ROW + lane + 64 * h];
                         cn_i8<DC>(v, P, a.alpha_num, a.alpha_shift);
 #pragma unroll
-                        for (int j = 0; j < DC; ++j)
-                            msg[(R * DC + j) * ROW + lane + 64 * h] = (msg_t)v[j];
+                        for (int j = 0; j < DC; ++j) {
+                            if constexpr (REG) m[R * DC + j] = (acc_t)v[j];
+                            else msg[(R * DC + j) * ROW + lane + 64 * h] = (msg_t)v[j];
+                        }
                     }
                 }
                 sched_group_end<FMT>(R);
@@ -491,15 +495,17 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                 if constexpr (REG) {
                     reload_table();
                     const uint32_t P = sb[0] << (31 - R);
-                    float v[DC], c[DC];
+                    acc_t v[DC], c[DC];
                     static_for<0, DC>([&](auto Jc) {
                         constexpr int j = decltype(Jc)::value;
                         constexpr int C = S::T.slot_bc[R][j];
                         // Q of the variable (C, t + s) this lane's check sees, minus the old r
                         v[j] = bperm(cn_src(shift_of(R * DC + j)), Qv[C]) - m[R * DC + j];
-                        c[j] = v[j];
+                        if constexpr (FMT == 0) c[j] = v[j];
+                        else c[j] = sat127(v[j]);      // check-node input
                     });
-                    cn_f32<DC>(c, P, a.alpha);
+                    if constexpr (FMT == 0) cn_f32<DC>(c, P, a.alpha);
+                    else cn_i8<DC>(c, P, a.alpha_num, a.alpha_shift);
                     static_for<0, DC>([&](auto Jc) {
                         constexpr int j = decltype(Jc)::value;
                         constexpr int C = S::T.slot_bc[R][j];
@@ -624,8 +630,16 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                             int sum = gamma_of(C, h);
 #pragma unroll
                             for (int i = 0; i < d; ++i) sum += r[i];
+                            if constexpr (REG) {
+                                static_for<0, d>([&](auto Ii) {
+                                    constexpr int i = decltype(Ii)::value;
+                                    constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
+                                    m[slot] = (acc_t)bperm(cn_src(shift_of(slot)), sat127(sum - (int)r[i]));
+                                });
+                            } else {
 #pragma unroll
-                            for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
+                                for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
+                            }
                             Q = sum;
                         }
                     } else if constexpr (REG) {
@@ -795,11 +809,11 @@ void k_wave(const DecodeArgs a) {
 template <bool PER_BIT, bool POST, bool WEIGHTED, int SCHED = 0>
 constexpr int reg_waves() { return (!PER_BIT && !POST) ? 3 : 2; }
 
-template <class S, int L, bool PER_BIT, bool POST, bool WEIGHTED = false, int SCHED = 0>
+template <class S, int L, bool PER_BIT, bool POST, bool WEIGHTED = false, int SCHED = 0, int FMT = 0>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(reg_waves<PER_BIT, POST, WEIGHTED, SCHED>())))
 void k_wreg(const DecodeArgs a) {
     using G = Geo<S, L>;
-    using Lay = WaveLds<S, L, 0, SCHED, 1, true>;
+    using Lay = WaveLds<S, L, FMT, SCHED, 1, true>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
     const int g = (threadIdx.x & 63) / G::SEG;
     const long shot = xcd_wave_index(blockIdx.x, gridDim.x) * G::SPW + g;
@@ -807,7 +821,7 @@ void k_wreg(const DecodeArgs a) {
     ref[0].shot = shot < a.batch ? shot : -1;
     ref[0].syn = a.syn + (shot < a.batch ? shot : 0) * G::SW;
     ref[0].err = a.err + (shot < a.batch ? shot : 0) * G::EW;
-    wave_decode<S, L, 0, SCHED, PER_BIT, POST, WEIGHTED, 1, true>(a, a.code, ref, lds);
+    wave_decode<S, L, FMT, SCHED, PER_BIT, POST, WEIGHTED, 1, true>(a, a.code, ref, lds);
 }
 
 // Neural min-sum inference (per-edge weights, per-shot priors, no posterior).
@@ -819,24 +833,25 @@ hipError_t launch_wreg_weighted(const DecodeArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <class S, int L, int SCHED>
+template <class S, int L, int SCHED, int FMT>
 void launch_wreg_sched(const LaunchKey &k, const DecodeArgs &a, unsigned grid, hipStream_t st) {
     if (k.per_bit) {
-        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, true, true, false, SCHED>), dim3(grid), dim3(64), 0, st, a);
-        else hipLaunchKernelGGL((k_wreg<S, L, true, false, false, SCHED>), dim3(grid), dim3(64), 0, st, a);
+        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, true, true, false, SCHED, FMT>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_wreg<S, L, true, false, false, SCHED, FMT>), dim3(grid), dim3(64), 0, st, a);
     } else {
-        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, false, true, false, SCHED>), dim3(grid), dim3(64), 0, st, a);
-        else hipLaunchKernelGGL((k_wreg<S, L, false, false, false, SCHED>), dim3(grid), dim3(64), 0, st, a);
+        if (k.post) hipLaunchKernelGGL((k_wreg<S, L, false, true, false, SCHED, FMT>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_wreg<S, L, false, false, false, SCHED, FMT>), dim3(grid), dim3(64), 0, st, a);
     }
 }
 
 template <class S, int L>
 hipError_t launch_wreg(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
-    if (k.fmt != 0) return hipErrorNotSupported;
     using G = Geo<S, L>;
     const unsigned grid = (unsigned)((a.batch + G::SPW - 1) / G::SPW);
-    if (k.sched == 0) launch_wreg_sched<S, L, 0>(k, a, grid, st);
-    else if (k.sched == 1) launch_wreg_sched<S, L, 1>(k, a, grid, st);
+    if (k.fmt == 0 && k.sched == 0) launch_wreg_sched<S, L, 0, 0>(k, a, grid, st);
+    else if (k.fmt == 0 && k.sched == 1) launch_wreg_sched<S, L, 1, 0>(k, a, grid, st);
+    else if (k.fmt == 1 && k.sched == 0) launch_wreg_sched<S, L, 0, 1>(k, a, grid, st);
+    else if (k.fmt == 1 && k.sched == 1) launch_wreg_sched<S, L, 1, 1>(k, a, grid, st);
     else return hipErrorNotSupported;
     return hipGetLastError();
 }

@@ -183,8 +183,18 @@ def test_register_resident_layered(L, per_bit):
     run_case(L, 100, 0.03, sched=1, per_bit=per_bit, max_iters=7, early_stop=False, seed=28, layout=REG)
 
 
+@pytest.mark.parametrize("L", [16, 64])
+@pytest.mark.parametrize("sched", [0, 1])
+def test_register_resident_int8_bit_exact(L, sched):
+    """int8 messages held as 32-bit integers in registers: bit-exact
+    decisions, flags, iterations and posteriors against the int8 oracle."""
+    run_case(L, 300 if L < 64 else 130, 0.05, fmt=1, sched=sched, seed=37, layout=REG)
+    run_case(L, 120, 0.04, fmt=1, sched=sched, per_bit=True, seed=38, layout=REG)
+    run_case(L, 60, 0.05, fmt=1, sched=sched, max_iters=5, early_stop=False, seed=39, layout=REG)
+
+
 def test_register_resident_rejects_unsupported():
-    for L, fmt, sched in ((64, 1, 0), (64, 1, 1), (128, 0, 0), (128, 0, 1)):
+    for L, fmt, sched in ((128, 0, 0), (128, 0, 1), (128, 1, 0)):
         c, H, dec = code(L)
         p = dec.params(fmt=fmt, sched=sched, layout=REG)
         err, conv, it, _ = dec.outputs(2)
@@ -197,7 +207,8 @@ def test_register_resident_rejects_unsupported():
 
 @pytest.mark.parametrize("fmt,sched,layout", [(0, 0, abi.QLDPC_LAYOUT_WAVE), (1, 0, abi.QLDPC_LAYOUT_WAVE),
                                               (0, 1, abi.QLDPC_LAYOUT_WAVE), (1, 1, abi.QLDPC_LAYOUT_WAVE),
-                                              (0, 0, abi.QLDPC_LAYOUT_WAVE_REG), (0, 1, abi.QLDPC_LAYOUT_WAVE_REG)])
+                                              (0, 0, abi.QLDPC_LAYOUT_WAVE_REG), (0, 1, abi.QLDPC_LAYOUT_WAVE_REG),
+                                              (1, 0, abi.QLDPC_LAYOUT_WAVE_REG), (1, 1, abi.QLDPC_LAYOUT_WAVE_REG)])
 def test_full_batch_sampled(fmt, sched, layout):
     """65536 shots at L = 64, p = 0.05, as the benchmark launches them; the
     oracle re-decodes a sample of shots one by one, and every converged shot
