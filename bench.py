@@ -49,11 +49,11 @@ def alu_ops_per_shot_iter(side) -> int:
     return int(9 * side.nnz + np.sum(deg * deg + deg))
 
 
-def recorded_traffic(kernel_sources):
+def recorded_traffic(kernel_sources, name="traffic_k_wreg_f32_flood_L64.json"):
     """HBM bytes per launch from the committed counter summary, or None when
     the kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_k_wreg_f32_flood_L64.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--latency-reqs", type=int, default=100000, help="requests per noise rate (0 = skip)")
     ap.add_argument("--mixed-shots", type=int, default=262144, help="mixed-code batch size (0 = skip)")
+    ap.add_argument("--hbm-shots", type=int, default=8192,
+                    help="shots of the L=256 code decoded with messages in HBM (0 = skip)")
     ap.add_argument("--seed", type=int, default=20250807)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run one plain device copy of MIB MiB (a known-size "
@@ -228,6 +230,45 @@ def main():
         finally:
             abi.qldpc_mixed_destroy(plan)
 
+    # ---------------- large lift: edge messages in HBM --------------------------
+    hbm = None
+    if args.hbm_shots > 0:
+        Lh, Bh = 256, args.hbm_shots
+        ch = lp.lp_code(Lh)
+        dh = Decoder(ch.hz, device=0)
+        t0h = time.time()
+        bh = noise.Batch(ch.hz, args.seed + 77, np.arange(Bh), 0.03)
+        gen_h = time.time() - t0h
+        syn_h = torch.from_numpy(bits.pack_bits(bh.s).view(np.int32)).to(dev)
+        pr_h = torch.from_numpy(bh.gamma).to(dev)
+        prm = dh.params(layout=abi.QLDPC_LAYOUT_HBM)
+        need = abi.qldpc_decode_workspace_bytes(dh.handle, prm, Bh)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        outh = dh.outputs(Bh)
+
+        def run_h():
+            abi.qldpc_decode_batch_ws(dh.handle, prm, Bh, syn_h, pr_h, *outh[:3], None, ws, need, stream)
+
+        run_h()
+        torch.cuda.synchronize()
+        e0h, e1h = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0h.record(stream)
+        for _ in range(3):
+            run_h()
+        e1h.record(stream)
+        torch.cuda.synchronize()
+        ms_h = e0h.elapsed_time(e1h) / 3
+        its_h = int(outh[2].to(torch.int64).sum().item())
+        edge_h = its_h * edge_model_bytes(ch.hz.nnz, 4) + Bh * ((ch.hz.m + 31) // 32 * 4 + 4 + (ch.hz.n + 31) // 32 * 4 + 2)
+        hbm = dict(value=Bh / (ms_h * 1e-3), unit="syndromes/s", code=f"LP 3x5, L={Lh} (N={ch.hz.n}, E={ch.hz.nnz})",
+                   shots=Bh, p=0.03, dtype="f32", ms_per_launch=ms_h, mean_iters=its_h / Bh,
+                   converged=float(outh[1].float().mean().item()), workspace_bytes=need,
+                   edge_model_GBps=edge_h / (ms_h * 1e-3) / 1e9,
+                   edge_model_frac=edge_h / (ms_h * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   hbm_traffic=recorded_traffic(None, "traffic_k_hbm_f32_L256.json"),
+                   layout="workgroup per shot (8 waves), edge messages in an HBM workspace", input_generation_s=gen_h)
+        del ws
+
     # ---------------- latency: one syndrome per request, host to host ---------
     latency = None
     if args.latency_reqs > 0:
@@ -332,6 +373,7 @@ def main():
         },
         "latency_us": latency,
         "mixed_batch": mixed,
+        "large_lift_hbm": hbm,
         "cpu_baseline": cpu,
         "ler": ler,
         "variants": variants,

@@ -71,7 +71,7 @@ typedef struct qldpc_code_s *qldpc_code;
  * and n = base_n * L, and the CSR must equal the expansion (checked).
  * The device kernels use the lift: they need the block pattern of a
  * lifted-product code LP(A, A*) with a 3 x 5 monomial base (H_Z or H_X
- * side) and L in {16, 32, 64, 128}; other valid matrices are accepted by
+ * side) and L in {16, 32, 64, 128, 256, 512}; other valid matrices are accepted by
  * qldpc_code_create only if they match, else QLDPC_ERR_UNSUPPORTED. */
 typedef struct {
     int32_t m, n;
@@ -125,6 +125,15 @@ typedef enum {
                                 shots when L < 64); throughput layout        */
     QLDPC_LAYOUT_BLOCK = 2,  /* one workgroup of several wavefronts decodes
                                 one shot; latency layout                     */
+    QLDPC_LAYOUT_HBM = 4,    /* one workgroup decodes one shot with its edge
+                                messages in a caller-provided device
+                                workspace (qldpc_decode_batch_ws): codes too
+                                large for on-chip messages; flooding with
+                                L in {128, 256, 512}; AUTO picks it for
+                                L >= 256, and, when a workspace can be given
+                                (qldpc_decode_workspace_bytes,
+                                qldpc_decode_batch_ws), for FP32 at L = 128
+                                with batch >= 512, where it is faster       */
     QLDPC_LAYOUT_WAVE_REG = 3 /* as WAVE, with every message (and, layered,
                                 every a-posteriori value) kept in the lanes'
                                 registers and moved between lanes by
@@ -165,6 +174,25 @@ qldpc_status qldpc_decode_batch(qldpc_code code, const qldpc_decode_params *para
                                 const uint32_t *syndromes, const void *priors, uint32_t *errors,
                                 uint8_t *converged, uint8_t *iters_used, float *posterior,
                                 void *stream);
+
+/* Device bytes of message workspace a decode of `batch` shots with these
+ * parameters needs when called through qldpc_decode_batch_ws: batch * 120
+ * * L * (4 for F32, 1 for I8Q4) when the chosen layout keeps messages in
+ * device memory (QLDPC_LAYOUT_HBM; see its AUTO rule), else 0.  Errors as
+ * qldpc_decode_batch. */
+qldpc_status qldpc_decode_workspace_bytes(qldpc_code code, const qldpc_decode_params *params, int32_t batch,
+                                          size_t *bytes);
+
+/* qldpc_decode_batch with a caller-owned device workspace of
+ * `workspace_bytes` (at least qldpc_decode_workspace_bytes; 256-byte
+ * aligned; contents need no initialisation and are garbage afterwards).
+ * Layouts that keep messages on chip ignore it (it may then be NULL).
+ * qldpc_decode_batch on a layout that needs a workspace returns
+ * QLDPC_ERR_UNSUPPORTED.  Calls sharing a workspace must not overlap. */
+qldpc_status qldpc_decode_batch_ws(qldpc_code code, const qldpc_decode_params *params, int32_t batch,
+                                   const uint32_t *syndromes, const void *priors, uint32_t *errors,
+                                   uint8_t *converged, uint8_t *iters_used, float *posterior, void *workspace,
+                                   size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Layout autotuner                                                          */

@@ -69,5 +69,16 @@ class Decoder:
         params = params or self.params()
         B = int(syndromes.shape[0])
         err, conv, it, post = out if out is not None else self.outputs(B, posterior)
-        abi.qldpc_decode_batch(self.handle, params, B, syndromes, priors, err, conv, it, post, stream)
+        need = abi.qldpc_decode_workspace_bytes(self.handle, params, B)
+        if need == 0:
+            abi.qldpc_decode_batch(self.handle, params, B, syndromes, priors, err, conv, it, post, stream)
+        else:
+            # messages in device memory (large lifts): a workspace from torch's allocator
+            import torch
+            ws = torch.empty(need + 256, dtype=torch.uint8, device=err.device)
+            base = ws.data_ptr()
+            off = (-base) % 256
+            abi.qldpc_decode_batch_ws(self.handle, params, B, syndromes, priors, err, conv, it, post,
+                                      base + off, need, stream)
+            self._ws = ws   # keep it alive until the next decode on this object
         return err, conv, it, post

@@ -26,7 +26,7 @@ QLDPC_ERR_NOT_READY = 6
 QLDPC_F32, QLDPC_I8Q4 = 0, 1
 QLDPC_FLOOD, QLDPC_LAYERED = 0, 1
 QLDPC_PRIOR_PER_SHOT, QLDPC_PRIOR_PER_BIT = 0, 1
-QLDPC_LAYOUT_AUTO, QLDPC_LAYOUT_WAVE, QLDPC_LAYOUT_BLOCK, QLDPC_LAYOUT_WAVE_REG = 0, 1, 2, 3
+QLDPC_LAYOUT_AUTO, QLDPC_LAYOUT_WAVE, QLDPC_LAYOUT_BLOCK, QLDPC_LAYOUT_WAVE_REG, QLDPC_LAYOUT_HBM = 0, 1, 2, 3, 4
 QLDPC_IO_COPY, QLDPC_IO_MAPPED, QLDPC_IO_RESIDENT = 0, 1, 2
 
 
@@ -85,7 +85,7 @@ def _load():
     except ImportError:
         pass
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_07879_amd.build` "
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2508_07879_amd/build.py` "
                           "(the decoder has no CPU fallback)")
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
@@ -98,6 +98,9 @@ def _load():
         "qldpc_code_destroy": ([vp], i32),
         "qldpc_code_info": ([vp, vp, vp, vp, vp, vp], i32),
         "qldpc_decode_batch": ([vp, C.POINTER(qldpc_decode_params), i32, vp, vp, vp, vp, vp, vp, vp], i32),
+        "qldpc_decode_workspace_bytes": ([vp, C.POINTER(qldpc_decode_params), i32, C.POINTER(C.c_size_t)], i32),
+        "qldpc_decode_batch_ws": ([vp, C.POINTER(qldpc_decode_params), i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t,
+                                   vp], i32),
         "qldpc_autotune": ([vp, C.POINTER(qldpc_decode_params), i32, vp, vp, vp, vp, vp, vp,
                             C.POINTER(qldpc_decode_params)], i32),
         "qldpc_tune_save": ([vp, C.c_char_p], i32),
@@ -138,7 +141,11 @@ def _check(st: int):
 
 
 def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+    if t is None:
+        return None
+    if isinstance(t, int):   # a raw device address
+        return C.c_void_p(t)
+    return C.c_void_p(t.data_ptr())
 
 
 def _stream(stream):
@@ -202,6 +209,20 @@ def qldpc_decode_batch(h, params: qldpc_decode_params, batch: int, syndromes, pr
     _check(lib.qldpc_decode_batch(h, C.byref(params), int(batch), _ptr(syndromes), _ptr(priors),
                                   _ptr(errors), _ptr(converged), _ptr(iters_used), _ptr(posterior),
                                   _stream(stream)))
+
+
+def qldpc_decode_workspace_bytes(h, params: qldpc_decode_params, batch: int) -> int:
+    n = C.c_size_t()
+    _check(lib.qldpc_decode_workspace_bytes(h, C.byref(params), int(batch), C.byref(n)))
+    return int(n.value)
+
+
+def qldpc_decode_batch_ws(h, params: qldpc_decode_params, batch: int, syndromes, priors, errors, converged,
+                          iters_used=None, posterior=None, workspace=None, workspace_bytes: int = 0,
+                          stream=None) -> None:
+    _check(lib.qldpc_decode_batch_ws(h, C.byref(params), int(batch), _ptr(syndromes), _ptr(priors), _ptr(errors),
+                                     _ptr(converged), _ptr(iters_used), _ptr(posterior), _ptr(workspace),
+                                     int(workspace_bytes), _stream(stream)))
 
 
 def qldpc_autotune(h, params: qldpc_decode_params, batch: int, syndromes, priors, errors, converged,

@@ -44,7 +44,7 @@ qldpc_status hip_fail(hipError_t e, const char *what) { return hip_error(e, what
 namespace qldpc {
 
 qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32_t batch, LaunchKey *key,
-                            DecodeArgs *a) {
+                            DecodeArgs *a, bool ws_ok) {
     if (!code || !p) return fail(QLDPC_ERR_INVALID_ARG, "decode: null code or params");
     if (batch < 0) return fail(QLDPC_ERR_INVALID_ARG, "decode: negative batch");
     if (p->max_iters < 1 || p->max_iters > 255)
@@ -55,7 +55,7 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     if (p->prior_mode != QLDPC_PRIOR_PER_SHOT && p->prior_mode != QLDPC_PRIOR_PER_BIT)
         return fail(QLDPC_ERR_INVALID_ARG, "decode: bad prior mode");
     if (!(p->alpha > 0.0f && p->alpha <= 1.0f)) return fail(QLDPC_ERR_INVALID_ARG, "decode: alpha must be in (0, 1]");
-    if (p->layout < QLDPC_LAYOUT_AUTO || p->layout > QLDPC_LAYOUT_WAVE_REG)
+    if (p->layout < QLDPC_LAYOUT_AUTO || p->layout > QLDPC_LAYOUT_HBM)
         return fail(QLDPC_ERR_INVALID_ARG, "decode: bad layout");
     if (p->waves_per_shot != 0 && p->waves_per_shot != 8 && p->waves_per_shot != 16)
         return fail(QLDPC_ERR_INVALID_ARG, "decode: waves_per_shot must be 0, 8 or 16");
@@ -83,6 +83,13 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     key->per_bit = p->prior_mode == QLDPC_PRIOR_PER_BIT;
     const bool block_ok = p->sched == QLDPC_FLOOD && code->L >= 64;
     int layout = p->layout, nw = p->waves_per_shot;
+    if (layout == QLDPC_LAYOUT_AUTO && code->L > 128) layout = QLDPC_LAYOUT_HBM;   // messages do not fit on chip
+    // FP32 flooding at L = 128 holds 77 KB of LDS per shot (two waves per compute
+    // unit); with a workspace, messages in device memory are faster there
+    // (3.5 vs 2.4 M syndromes/s on MI355X, 32768 shots, p = 0.03).
+    if (layout == QLDPC_LAYOUT_AUTO && ws_ok && code->L == 128 && p->fmt == QLDPC_F32 && p->sched == QLDPC_FLOOD &&
+        batch >= 512)
+        layout = QLDPC_LAYOUT_HBM;
     if (layout == QLDPC_LAYOUT_AUTO) {
         bool found = false;
         {
@@ -107,6 +114,10 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     }
     if (layout == QLDPC_LAYOUT_WAVE_REG && code->L > 64)
         return fail(QLDPC_ERR_UNSUPPORTED, "decode: register-resident messages need L <= 64");
+    if (layout == QLDPC_LAYOUT_HBM && (p->sched != QLDPC_FLOOD || code->L < 128))
+        return fail(QLDPC_ERR_UNSUPPORTED, "decode: the HBM layout needs flooding and L in {128, 256, 512}");
+    if (layout != QLDPC_LAYOUT_HBM && code->L > 128)
+        return fail(QLDPC_ERR_UNSUPPORTED, "decode: lifts above 128 keep messages in HBM (QLDPC_LAYOUT_HBM)");
     key->layout = layout;
     key->nw = nw;
     return QLDPC_OK;
@@ -207,8 +218,8 @@ qldpc_status qldpc_code_create(const qldpc_code_desc *d, int32_t device, qldpc_c
     if (which < 0)
         return fail(QLDPC_ERR_UNSUPPORTED,
                     "code_create: block pattern is not a 3x5 lifted-product H_Z or H_X pattern");
-    if (L != 16 && L != 32 && L != 64 && L != 128)
-        return fail(QLDPC_ERR_UNSUPPORTED, "code_create: lift size must be 16, 32, 64 or 128");
+    if (L != 16 && L != 32 && L != 64 && L != 128 && L != 256 && L != 512)
+        return fail(QLDPC_ERR_UNSUPPORTED, "code_create: lift size must be 16, 32, 64, 128, 256 or 512");
 
     auto *code = new (std::nothrow) qldpc_code_s();
     if (!code) return fail(QLDPC_ERR_OUT_OF_MEMORY, "code_create: host allocation failed");
@@ -273,14 +284,31 @@ qldpc_status qldpc_code_info(qldpc_code c, int32_t *m, int32_t *n, int32_t *nnz,
     return QLDPC_OK;
 }
 
-qldpc_status qldpc_decode_batch(qldpc_code code, const qldpc_decode_params *p, int32_t batch,
-                                const uint32_t *syn, const void *priors, uint32_t *err,
-                                uint8_t *conv, uint8_t *iters, float *post, void *stream) {
+namespace {
+
+// Bytes of message workspace for key k and `batch` shots (0 when on chip).
+size_t workspace_bytes_for(const qldpc_code code, const LaunchKey &k, int32_t batch) {
+    if (k.layout != QLDPC_LAYOUT_HBM) return 0;
+    return (size_t)batch * 120 * (size_t)code->L * (k.fmt == QLDPC_F32 ? 4 : 1);
+}
+
+qldpc_status decode_impl(qldpc_code code, const qldpc_decode_params *p, int32_t batch, const uint32_t *syn,
+                         const void *priors, uint32_t *err, uint8_t *conv, uint8_t *iters, float *post, bool with_ws,
+                         void *ws, size_t ws_bytes, void *stream, const char *who) {
     LaunchKey k{};
     DecodeArgs a{};
-    qldpc_status st = prepare_decode(code, p, batch, &k, &a);
+    qldpc_status st = prepare_decode(code, p, batch, &k, &a, with_ws);
     if (st != QLDPC_OK || batch == 0) return st;
-    if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, "decode_batch: null buffer");
+    if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, std::string(who) + ": null buffer");
+    const size_t need = workspace_bytes_for(code, k, batch);
+    if (need > 0) {
+        if (!with_ws)
+            return fail(QLDPC_ERR_UNSUPPORTED, std::string(who) +
+                                                   ": this layout keeps messages in a device workspace; use "
+                                                   "qldpc_decode_batch_ws");
+        if (!ws || ws_bytes < need || ((uintptr_t)ws & 255) != 0)
+            return fail(QLDPC_ERR_INVALID_ARG, std::string(who) + ": workspace missing, too small or not 256-byte aligned");
+    }
     a.syn = syn;
     a.prior = priors;
     a.err = err;
@@ -288,11 +316,39 @@ qldpc_status qldpc_decode_batch(qldpc_code code, const qldpc_decode_params *p, i
     a.iters = iters;
     a.post = post;
     k.post = post != nullptr;
-    const hipError_t e = launch_decode(k, a, (hipStream_t)stream);
+    const hipError_t e = k.layout == QLDPC_LAYOUT_HBM ? launch_hbm_decode(k, a, ws, (hipStream_t)stream)
+                                                      : launch_decode(k, a, (hipStream_t)stream);
     if (e == hipErrorNotSupported)
-        return fail(QLDPC_ERR_UNSUPPORTED, "decode_batch: no kernel for this format/schedule/layout/L");
-    if (e != hipSuccess) return hip_fail(e, "decode_batch launch");
+        return fail(QLDPC_ERR_UNSUPPORTED, std::string(who) + ": no kernel for this format/schedule/layout/L");
+    if (e != hipSuccess) return hip_fail(e, "decode launch");
     return QLDPC_OK;
+}
+
+}  // namespace
+
+qldpc_status qldpc_decode_batch(qldpc_code code, const qldpc_decode_params *p, int32_t batch,
+                                const uint32_t *syn, const void *priors, uint32_t *err,
+                                uint8_t *conv, uint8_t *iters, float *post, void *stream) {
+    return decode_impl(code, p, batch, syn, priors, err, conv, iters, post, false, nullptr, 0, stream, "decode_batch");
+}
+
+qldpc_status qldpc_decode_workspace_bytes(qldpc_code code, const qldpc_decode_params *p, int32_t batch,
+                                          size_t *bytes) {
+    if (!bytes) return fail(QLDPC_ERR_INVALID_ARG, "decode_workspace_bytes: null output");
+    LaunchKey k{};
+    DecodeArgs a{};
+    qldpc_status st = prepare_decode(code, p, batch, &k, &a, true);
+    if (st != QLDPC_OK) return st;
+    *bytes = workspace_bytes_for(code, k, batch);
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_decode_batch_ws(qldpc_code code, const qldpc_decode_params *p, int32_t batch,
+                                   const uint32_t *syn, const void *priors, uint32_t *err, uint8_t *conv,
+                                   uint8_t *iters, float *post, void *workspace, size_t workspace_bytes,
+                                   void *stream) {
+    return decode_impl(code, p, batch, syn, priors, err, conv, iters, post, true, workspace, workspace_bytes, stream,
+                       "decode_batch_ws");
 }
 
 qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, int32_t batch,
@@ -301,6 +357,7 @@ qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, 
     if (!code || !params || !best) return fail(QLDPC_ERR_INVALID_ARG, "autotune: null argument");
     if (batch <= 0) return fail(QLDPC_ERR_INVALID_ARG, "autotune: batch must be positive");
     if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, "autotune: null buffer");
+    if (code->L > 128) return fail(QLDPC_ERR_UNSUPPORTED, "autotune: lifts above 128 have one layout (HBM messages)");
     struct Cand { int layout, nw; };
     std::vector<Cand> cands = {{QLDPC_LAYOUT_WAVE, 0}};
     if (code->L <= 64) cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});

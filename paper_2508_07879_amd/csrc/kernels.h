@@ -81,6 +81,8 @@ struct LaunchKey {
 
 // Returns hipErrorNotSupported when no kernel exists for the key.
 hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t stream);
+// Launches the HBM-message workgroup decoder (layout 4) on workspace `ws`.
+hipError_t launch_hbm_decode(const LaunchKey &k, const DecodeArgs &a, void *ws, hipStream_t stream);
 // Launches the resident decoder (workgroup layout only) with `grid` shot slots.
 hipError_t launch_resident_decode(const LaunchKey &k, const ResidentArgs &r, int grid, hipStream_t stream);
 

@@ -262,6 +262,8 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
     DecodeArgs a{};
     qldpc_status st = prepare_decode(code, &prm, max_batch, &k, &a);   // validates params
     if (st != QLDPC_OK) return st;
+    if (k.layout == QLDPC_LAYOUT_HBM)
+        return set_error(QLDPC_ERR_UNSUPPORTED, "session_create: sessions keep messages on chip (L <= 128)");
     params = &prm;
     auto *s = new (std::nothrow) qldpc_session_s();
     if (!s) return set_error(QLDPC_ERR_OUT_OF_MEMORY, "session_create: host allocation");

@@ -1,0 +1,135 @@
+"""Messages in device memory (QLDPC_LAYOUT_HBM) for lifts whose messages do
+not fit on chip (L = 256, 512), and for L = 128 where the on-chip layouts
+give the reference: same decisions, flags, iteration counts and posteriors
+as the oracle (FP32 within 1e-5, int8 bit-exact), the workspace contract,
+and the rejections."""
+import numpy as np
+import pytest
+
+from workload import bits, lp, noise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2508_07879_amd import Decoder, abi  # noqa: E402
+
+from gpu_util import assert_parity, gpu_decode, oracle_decode, to_dev  # noqa: E402
+
+HBM, WAVE = abi.QLDPC_LAYOUT_HBM, abi.QLDPC_LAYOUT_WAVE
+_sides = {}
+
+
+def side(L, which=0):
+    if (L, which) not in _sides:
+        c = lp.lp_code(L)
+        sd = c.hx if which else c.hz
+        _sides[(L, which)] = (c, sd, sd.dense(), Decoder(sd))
+    return _sides[(L, which)]
+
+
+def case(L, shots, p, fmt=0, per_bit=False, which=0, seed=101, max_iters=32, early_stop=True, layout=0):
+    c, sd, H, dec = side(L, which)
+    b = noise.Batch(sd, seed, np.arange(shots), p)
+    if fmt == 0:
+        prior = b.gamma
+        if per_bit:
+            j = noise.rng.uniform(seed, noise.rng.DOMAIN_PRIOR, np.arange(shots)[:, None], np.arange(sd.n)[None, :])
+            prior = (b.prior_bits() * (0.5 + j)).astype(np.float32)
+        scale = prior if per_bit else b.gamma[:, None]
+    else:
+        prior = b.gamma_q4()
+        if per_bit:
+            prior = np.repeat(prior[:, None], sd.n, axis=1)
+        scale = None
+    g = gpu_decode(dec, b.s, prior, fmt=fmt, per_bit=per_bit, max_iters=max_iters, early_stop=early_stop,
+                   layout=layout)
+    o = oracle_decode(H, b.s, prior, fmt=fmt, max_iters=max_iters, early_stop=early_stop)
+    assert_parity(g, o, scale, fmt, tag=f"HBM L={L} fmt={fmt} pb={per_bit} which={which} layout={layout}")
+    return g, o
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_L256_matches_oracle(fmt):
+    g, _ = case(256, 48, 0.05, fmt=fmt)
+    ok = g[1] == 1
+    c, sd, H, dec = side(256)
+    assert ok.any()
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_L256_per_bit_fixed_iterations_and_hx(fmt):
+    case(256, 24, 0.04, fmt=fmt, per_bit=True, seed=102)
+    case(256, 16, 0.05, fmt=fmt, max_iters=6, early_stop=False, seed=103)
+    case(256, 24, 0.05, fmt=fmt, which=1, seed=104)
+
+
+def test_L512_matches_oracle():
+    case(512, 12, 0.04, seed=105)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_L128_hbm_equals_lds_layout(fmt):
+    c, sd, H, dec = side(128)
+    b = noise.Batch(sd, 106 + fmt, np.arange(96), 0.05)
+    prior = b.gamma if fmt == 0 else b.gamma_q4()
+    g_h = gpu_decode(dec, b.s, prior, fmt=fmt, layout=HBM)
+    g_w = gpu_decode(dec, b.s, prior, fmt=fmt, layout=WAVE)
+    for x, y in zip(g_h, g_w):
+        assert np.array_equal(x, y)
+    o = oracle_decode(H, b.s, prior, fmt=fmt)
+    assert_parity(g_h, o, b.gamma[:, None] if fmt == 0 else None, fmt, tag=f"HBM L=128 fmt={fmt}")
+
+
+def test_workspace_contract_and_rejections():
+    c, sd, H, dec = side(256)
+    B = 8
+    p32 = dec.params()
+    assert abi.qldpc_decode_workspace_bytes(dec.handle, p32, B) == B * 120 * 256 * 4
+    assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(fmt=abi.QLDPC_I8Q4), B) == B * 120 * 256
+    c64, sd64, _, dec64 = side(64)
+    assert abi.qldpc_decode_workspace_bytes(dec64.handle, dec64.params(), B) == 0
+    # L = 128: AUTO with a workspace takes device-memory messages for FP32 batches >= 512
+    c128, sd128, _, dec128 = side(128)
+    assert abi.qldpc_decode_workspace_bytes(dec128.handle, dec128.params(), 1024) == 1024 * 120 * 128 * 4
+    assert abi.qldpc_decode_workspace_bytes(dec128.handle, dec128.params(), 100) == 0
+    assert abi.qldpc_decode_workspace_bytes(dec128.handle, dec128.params(fmt=abi.QLDPC_I8Q4), 1024) == 0
+    syn = torch.zeros((B, dec.syn_words), dtype=torch.int32, device="cuda")
+    pr = torch.full((B,), 3.0, device="cuda")
+    err, conv, it, _ = dec.outputs(B)
+    with pytest.raises(abi.QldpcError) as ei:        # messages would need a workspace
+        abi.qldpc_decode_batch(dec.handle, p32, B, syn, pr, err, conv, it, None)
+    assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED
+    ws = torch.empty(B * 120 * 256 * 4, dtype=torch.uint8, device="cuda")
+    with pytest.raises(abi.QldpcError) as ei:        # one byte short
+        abi.qldpc_decode_batch_ws(dec.handle, p32, B, syn, pr, err, conv, it, None, ws, ws.numel() - 1)
+    assert ei.value.status == abi.QLDPC_ERR_INVALID_ARG
+    abi.qldpc_decode_batch_ws(dec.handle, p32, B, syn, pr, err, conv, it, None, ws, ws.numel())
+    torch.cuda.synchronize()
+    assert torch.all(conv == 1) and torch.all(err == 0)      # zero syndrome, positive priors
+    for bad in (dec.params(sched=abi.QLDPC_LAYERED), dec.params(layout=WAVE), dec.params(layout=abi.QLDPC_LAYOUT_BLOCK)):
+        with pytest.raises(abi.QldpcError) as ei:
+            abi.qldpc_decode_workspace_bytes(dec.handle, bad, B)
+        assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED
+    with pytest.raises(abi.QldpcError) as ei:
+        abi.qldpc_session_create(dec.handle, p32, 1, abi.QLDPC_IO_MAPPED)
+    assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED
+
+
+def test_L256_large_batch_sampled():
+    """16384 shots at p = 0.05 in one launch (a 2 GB message workspace):
+    converged shots reproduce their syndromes and a sample matches the
+    oracle shot by shot."""
+    c, sd, H, dec = side(256)
+    B = 16384
+    b = noise.Batch(sd, 107, np.arange(B), 0.05)
+    e, conv, it, _ = gpu_decode(dec, b.s, b.gamma, posterior=False)
+    ok = conv == 1
+    assert ok.mean() > 0.5
+    assert np.array_equal(noise.syndromes(sd, e[ok]), b.s[ok])
+    idx = np.unique(np.concatenate([np.arange(0, B, 2048), [B - 1], np.nonzero(~ok)[0][:4]]))
+    o = oracle_decode(H, b.s[idx], b.gamma[idx])
+    assert np.array_equal(e[idx], o.e) and np.array_equal(conv[idx], o.converged)
+    assert np.array_equal(it[idx], o.iters)
