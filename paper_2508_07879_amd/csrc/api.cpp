@@ -251,14 +251,14 @@ qldpc_status qldpc_code_create(const qldpc_code_desc *d, int32_t device, qldpc_c
     if (e != hipSuccess) { delete code; return hip_fail(e, "hipSetDevice"); }
     e = hipMalloc(&code->dev, sizeof(DevCode));
     if (e != hipSuccess) {
-        hipSetDevice(prev);
+        (void)hipSetDevice(prev);
         delete code;
         return fail(QLDPC_ERR_OUT_OF_MEMORY, "code_create: hipMalloc failed");
     }
     e = hipMemcpy(code->dev, &host, sizeof(DevCode), hipMemcpyHostToDevice);
-    hipSetDevice(prev);
+    (void)hipSetDevice(prev);
     if (e != hipSuccess) {
-        hipFree(code->dev);
+        (void)hipFree(code->dev);
         delete code;
         return hip_fail(e, "code_create: upload");
     }
@@ -268,7 +268,7 @@ qldpc_status qldpc_code_create(const qldpc_code_desc *d, int32_t device, qldpc_c
 
 qldpc_status qldpc_code_destroy(qldpc_code code) {
     if (!code) return QLDPC_OK;
-    if (code->dev) hipFree(code->dev);
+    if (code->dev) (void)hipFree(code->dev);
     delete code;
     return QLDPC_OK;
 }
@@ -370,7 +370,7 @@ qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, 
     hipError_t he = hipEventCreate(&e0);
     if (he != hipSuccess) return hip_fail(he, "autotune: event");
     he = hipEventCreate(&e1);
-    if (he != hipSuccess) { hipEventDestroy(e0); return hip_fail(he, "autotune: event"); }
+    if (he != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(he, "autotune: event"); }
     TuneChoice bestc{};
     bestc.ms = 1e30f;
     qldpc_status rc = QLDPC_OK;
@@ -381,20 +381,21 @@ qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, 
         rc = qldpc_decode_batch(code, &q, batch, syn, priors, err, conv, iters, nullptr, stream);  // warm-up
         if (rc != QLDPC_OK) break;
         const int reps = 3;
-        hipEventRecord(e0, st);
+        he = hipEventRecord(e0, st);
+        if (he != hipSuccess) { rc = hip_fail(he, "autotune: record"); break; }
         for (int r = 0; r < reps && rc == QLDPC_OK; ++r)
             rc = qldpc_decode_batch(code, &q, batch, syn, priors, err, conv, iters, nullptr, stream);
-        hipEventRecord(e1, st);
+        he = hipEventRecord(e1, st);
         if (rc != QLDPC_OK) break;
-        he = hipEventSynchronize(e1);
-        if (he != hipSuccess) { rc = hip_fail(he, "autotune: synchronize"); break; }
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) { rc = hip_fail(he, "autotune: timing"); break; }
         ms /= reps;
         if (ms < bestc.ms) bestc = TuneChoice{c.layout, c.nw, ms};
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != QLDPC_OK) return rc;
     {
         std::lock_guard<std::mutex> g(code->tune_mu);

@@ -106,7 +106,7 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
     std::copy(codes, codes + ncodes, x->codes);
     x->params = *params;
     int cus = 256;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
     x->waves = 12 * cus;     // register grids: up to three waves per SIMD
     x->waves128 = 4 * cus;   // L = 128: two 61 KB waves fit per CU; two rounds
     for (int c = 0; c < ncodes; ++c) {
@@ -129,8 +129,8 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
 
 qldpc_status qldpc_mixed_destroy(qldpc_mixed x) {
     if (!x) return QLDPC_OK;
-    for (auto &kv : x->graphs) hipGraphExecDestroy(kv.second);
-    if (x->scratch) hipFree(x->scratch);
+    for (auto &kv : x->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (x->scratch) (void)hipFree(x->scratch);
     delete x;
     return QLDPC_OK;
 }
@@ -153,7 +153,7 @@ qldpc_status qldpc_mixed_decode(qldpc_mixed x, int32_t batch, const int32_t *sho
     hipGraphExec_t ex = nullptr;
     if (it == x->graphs.end()) {
         if (x->graphs.size() >= 16) {
-            for (auto &kv : x->graphs) hipGraphExecDestroy(kv.second);
+            for (auto &kv : x->graphs) (void)hipGraphExecDestroy(kv.second);
             x->graphs.clear();
         }
         // capture on a private stream so the caller's stream is never in capture mode
@@ -162,20 +162,20 @@ qldpc_status qldpc_mixed_decode(qldpc_mixed x, int32_t batch, const int32_t *sho
         if (e != hipSuccess) return hip_error(e, "mixed_decode: capture stream");
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
-            hipStreamDestroy(cs);
+            (void)hipStreamDestroy(cs);
             return hip_error(e, "mixed_decode: begin capture");
         }
         qldpc_status s2 = enqueue(x, batch, shot_code, syn_off, err_off, syn, prior, err, conv, iters, cs, x->waves);
         hipGraph_t gr = nullptr;
         e = hipStreamEndCapture(cs, &gr);
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         if (s2 != QLDPC_OK) {
-            if (gr) hipGraphDestroy(gr);
+            if (gr) (void)hipGraphDestroy(gr);
             return s2;
         }
         if (e != hipSuccess) return hip_error(e, "mixed_decode: end capture");
         e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-        hipGraphDestroy(gr);
+        (void)hipGraphDestroy(gr);
         if (e != hipSuccess) return hip_error(e, "mixed_decode: instantiate");
         x->graphs[key] = ex;
     } else {
@@ -194,12 +194,12 @@ qldpc_status qldpc_mixed_autotune(qldpc_mixed x, int32_t batch, const int32_t *s
     if (!shot_code || !syn_off || !err_off || !syn || !prior || !err || !conv)
         return set_error(QLDPC_ERR_INVALID_ARG, "mixed_autotune: null buffer");
     int cus = 256;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return set_error(QLDPC_ERR_DEVICE, "mixed_autotune: event");
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return set_error(QLDPC_ERR_DEVICE, "mixed_autotune: event");
     }
     float best = 1e30f;
@@ -209,21 +209,25 @@ qldpc_status qldpc_mixed_autotune(qldpc_mixed x, int32_t batch, const int32_t *s
         const int w = mult * cus;
         rc = enqueue(x, batch, shot_code, syn_off, err_off, syn, prior, err, conv, iters, st, w);
         if (rc != QLDPC_OK) break;
-        hipEventRecord(e0, st);
-        for (int r = 0; r < 3 && rc == QLDPC_OK; ++r)
+        hipError_t he = hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && rc == QLDPC_OK && he == hipSuccess; ++r)
             rc = enqueue(x, batch, shot_code, syn_off, err_off, syn, prior, err, conv, iters, st, w);
-        hipEventRecord(e1, st);
+        if (he == hipSuccess) he = hipEventRecord(e1, st);
         if (rc != QLDPC_OK) break;
-        hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+            rc = hip_error(he, "mixed_autotune: timing");
+            break;
+        }
         if (ms < best) {
             best = ms;
             bw = w;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != QLDPC_OK) return rc;
     std::lock_guard<std::mutex> g(x->mu);
     x->waves = bw;

@@ -83,21 +83,21 @@ bool resident_stop(qldpc_session s) {
 }
 
 void release(qldpc_session s) {
-    if (s->ring) hipHostFree(s->ring);
-    if (s->ev_exit) hipEventDestroy(s->ev_exit);
-    if (s->d_cmd) hipFree(s->d_cmd);
-    for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
-    if (s->d_syn) hipFree(s->d_syn);
-    if (s->d_prior) hipFree(s->d_prior);
-    if (s->d_err) hipFree(s->d_err);
-    if (s->d_conv) hipFree(s->d_conv);
-    if (s->d_iters) hipFree(s->d_iters);
-    if (s->h_syn) hipHostFree(s->h_syn);
-    if (s->h_prior) hipHostFree(s->h_prior);
-    if (s->h_err) hipHostFree(s->h_err);
-    if (s->h_conv) hipHostFree(s->h_conv);
-    if (s->h_iters) hipHostFree(s->h_iters);
-    if (s->stream) hipStreamDestroy(s->stream);
+    if (s->ring) (void)hipHostFree(s->ring);
+    if (s->ev_exit) (void)hipEventDestroy(s->ev_exit);
+    if (s->d_cmd) (void)hipFree(s->d_cmd);
+    for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (s->d_syn) (void)hipFree(s->d_syn);
+    if (s->d_prior) (void)hipFree(s->d_prior);
+    if (s->d_err) (void)hipFree(s->d_err);
+    if (s->d_conv) (void)hipFree(s->d_conv);
+    if (s->d_iters) (void)hipFree(s->d_iters);
+    if (s->h_syn) (void)hipHostFree(s->h_syn);
+    if (s->h_prior) (void)hipHostFree(s->h_prior);
+    if (s->h_err) (void)hipHostFree(s->h_err);
+    if (s->h_conv) (void)hipHostFree(s->h_conv);
+    if (s->h_iters) (void)hipHostFree(s->h_iters);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
 
@@ -139,22 +139,24 @@ qldpc_status graph_for(qldpc_session s, int32_t batch, hipGraphExec_t *out) {
     qldpc_status st = QLDPC_OK;
     const size_t sb = (size_t)batch * s->syn_words * 4, pb = (size_t)batch * s->prior_bytes_per_shot;
     const size_t eb = (size_t)batch * s->err_words * 4;
-    hipMemcpyAsync(s->d_syn, s->h_syn, sb, hipMemcpyHostToDevice, s->stream);
-    hipMemcpyAsync(s->d_prior, s->h_prior, pb, hipMemcpyHostToDevice, s->stream);
-    st = enqueue(s, batch);
-    hipMemcpyAsync(s->h_err, s->d_err, eb, hipMemcpyDeviceToHost, s->stream);
-    hipMemcpyAsync(s->h_conv, s->d_conv, (size_t)batch, hipMemcpyDeviceToHost, s->stream);
-    hipMemcpyAsync(s->h_iters, s->d_iters, (size_t)batch, hipMemcpyDeviceToHost, s->stream);
+    hipError_t ce = hipMemcpyAsync(s->d_syn, s->h_syn, sb, hipMemcpyHostToDevice, s->stream);
+    if (ce == hipSuccess) ce = hipMemcpyAsync(s->d_prior, s->h_prior, pb, hipMemcpyHostToDevice, s->stream);
+    if (ce == hipSuccess) st = enqueue(s, batch);
+    if (ce == hipSuccess && st == QLDPC_OK) ce = hipMemcpyAsync(s->h_err, s->d_err, eb, hipMemcpyDeviceToHost, s->stream);
+    if (ce == hipSuccess && st == QLDPC_OK)
+        ce = hipMemcpyAsync(s->h_conv, s->d_conv, (size_t)batch, hipMemcpyDeviceToHost, s->stream);
+    if (ce == hipSuccess && st == QLDPC_OK)
+        ce = hipMemcpyAsync(s->h_iters, s->d_iters, (size_t)batch, hipMemcpyDeviceToHost, s->stream);
     hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(s->stream, &g);
-    if (st != QLDPC_OK) {
-        if (g) hipGraphDestroy(g);
-        return st;
+    e = hipStreamEndCapture(s->stream, &g);   // always end the capture, whatever failed inside it
+    if (st != QLDPC_OK || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != QLDPC_OK ? st : hip_error(ce, "session: capture copy");
     }
     if (e != hipSuccess) return hip_error(e, "session: end capture");
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_error(e, "session: instantiate");
     s->graphs[batch] = ex;
     *out = ex;
@@ -345,7 +347,7 @@ qldpc_status qldpc_session_destroy(qldpc_session s) {
     if (!s) return QLDPC_OK;
     if (!resident_stop(s))   // leave the buffers to a grid that still runs rather than free them under it
         return set_error(QLDPC_ERR_DEVICE, "session_destroy: the resident decoder did not exit; session leaked");
-    if (s->stream) hipStreamSynchronize(s->stream);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
     release(s);
     return QLDPC_OK;
 }
