@@ -287,9 +287,10 @@ typedef struct qldpc_mixed_s *qldpc_mixed;
 /* Plan over 1..8 code objects on one device for batches of up to
  * max_batch shots (FP32 flooding, per-shot priors; params gives alpha,
  * iterations and early stop; lifts 16, 32, 64 and 128).  Allocates
- * 4 * (max_batch + 20) bytes of device scratch.  One persistent grid per lift
- * size decodes its shots: messages in registers for L <= 64, in LDS for
- * L = 128.  use_graph = 1: every distinct argument set is captured
+ * 4 * (max_batch + 24) bytes of device scratch, plus 61440 bytes per L = 128
+ * workgroup (four per compute unit) when a code has L = 128.  One persistent
+ * grid per (pattern, lift size) decodes its shots: messages in registers for
+ * L <= 64, in that HBM workspace for L = 128.  use_graph = 1: every distinct argument set is captured
  * once as a hipGraph (bucketing kernels + persistent decoders) and
  * replayed. */
 qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const qldpc_decode_params *params,

@@ -46,8 +46,15 @@ __device__ __forceinline__ uint64_t rot_word(const uint64_t *e, uint32_t s, int 
     return (w0 >> r) | (w1 << (64u - r));
 }
 
+// Decodes shot `shot` of the code whose shift table is `code_table`
+// (syndrome words at syn, error words to err, flags and priors indexed by
+// shot) with the whole workgroup, messages at msg.  a.code is not used: the
+// mixed-code path passes each shot's own table.  Every thread of the
+// workgroup must call it; `lds` holds HbmLds<S, L, NW>::bytes.
 template <class S, int L, int FMT, int NW, bool PER_BIT, bool POST>
-__global__ __launch_bounds__(64 * NW) void k_hbm(const DecodeArgs a, void *workspace) {
+__device__ __forceinline__ void hbm_decode(const DecodeArgs &a, const DevCode *code_table, const long shot,
+                                           const uint32_t *syn, uint32_t *err, typename Fmt<FMT>::msg_t *msg,
+                                           unsigned char *lds) {
     using namespace wave;
     static_assert(L >= 64 && L % 64 == 0, "HBM layout: L a multiple of 64");
     using Lay = HbmLds<S, L, NW>;
@@ -58,20 +65,16 @@ __global__ __launch_bounds__(64 * NW) void k_hbm(const DecodeArgs a, void *works
     constexpr int N = NB * L, SW = (MB * L + 31) / 32, EW = (NB * L + 31) / 32;
     constexpr int CN_ITEMS = MB * PPL, VN_ITEMS = NB * PPL;
 
-    __shared__ __attribute__((aligned(16))) unsigned char lds[Lay::bytes];
     uint64_t *emask = reinterpret_cast<uint64_t *>(lds + Lay::e_off);
     uint32_t *flag = reinterpret_cast<uint32_t *>(lds + Lay::f_off);
     uint32_t *synw = reinterpret_cast<uint32_t *>(lds + Lay::s_off);
 
-    const long shot = blockIdx.x;
-    if (a.only && a.only[shot] == 0) return;   // uniform over the workgroup
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const CodePtr code = const_code(a.code);
-    msg_t *msg = static_cast<msg_t *>(workspace) + shot * (long)(S::SLOTS * L);
+    const CodePtr code = const_code(code_table);
     const prior_t *prior = static_cast<const prior_t *>(a.prior);
 
-    for (int w = threadIdx.x; w < SW; w += 64 * NW) synw[w] = a.syn[shot * SW + w];
+    for (int w = threadIdx.x; w < SW; w += 64 * NW) synw[w] = syn[w];
     acc_t gshot = 0;
     if constexpr (!PER_BIT) {
         gshot = (acc_t)prior[shot];
@@ -111,7 +114,7 @@ __global__ __launch_bounds__(64 * NW) void k_hbm(const DecodeArgs a, void *works
     auto emit = [&](int k, bool conv) {
         for (int w = threadIdx.x; w < EW; w += 64 * NW) {
             const uint64_t m = emask[(w * 32) / 64];
-            a.err[shot * EW + w] = (uint32_t)(m >> ((w * 32) % 64));
+            err[w] = (uint32_t)(m >> ((w * 32) % 64));
         }
         if (threadIdx.x == 0) {
             a.conv[shot] = conv ? 1 : 0;
@@ -221,6 +224,17 @@ __global__ __launch_bounds__(64 * NW) void k_hbm(const DecodeArgs a, void *works
     test_rows((k + 1) & 1);
     __syncthreads();
     emit(k, __builtin_amdgcn_readfirstlane(flag[(k + 1) & 1]) == 0);
+}
+
+template <class S, int L, int FMT, int NW, bool PER_BIT, bool POST>
+__global__ __launch_bounds__(64 * NW) void k_hbm(const DecodeArgs a, void *workspace) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[HbmLds<S, L, NW>::bytes];
+    constexpr int SW = (S::MB * L + 31) / 32, EW = (S::NB * L + 31) / 32;
+    const long shot = blockIdx.x;
+    if (a.only && a.only[shot] == 0) return;   // uniform over the workgroup
+    using msg_t = typename Fmt<FMT>::msg_t;
+    msg_t *msg = static_cast<msg_t *>(workspace) + shot * (long)(S::SLOTS * L);
+    hbm_decode<S, L, FMT, NW, PER_BIT, POST>(a, a.code, shot, a.syn + shot * SW, a.err + shot * EW, msg, lds);
 }
 
 template <class S, int L, int FMT, int NW>

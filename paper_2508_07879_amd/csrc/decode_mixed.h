@@ -8,16 +8,19 @@
 // wavefronts per (block pattern, lift size) then claims tiles of same-code
 // shots from its own atomic counter until none are left: for L <= 64 every
 // message stays in registers (one 64-lane group of 64 / L shots per tile),
-// for L = 128 in LDS (one shot per tile).  Codes of both patterns (H_Z and
+// for L = 128 in a plan-owned HBM workspace, one slot per persistent
+// workgroup of 8 waves (one shot per tile).  Codes of both patterns (H_Z and
 // H_X of one CSS code, say) can share a batch, so both sides of a code are
 // decoded in one launch sequence.  Each shot's result depends only on its
 // own syndrome and prior, never on its tile mates or grid.
 #pragma once
+#include "decode_hbm.h"
 #include "decode_wave.h"
 
 namespace qldpc {
 
 constexpr int kMaxMixCodes = 8;
+constexpr int kMixHbmWaves = 8;   // waves per workgroup of the L = 128 grid
 
 struct MixedArgs {
     DecodeArgs base;                       // alpha, iterations, priors, conv / iters outputs
@@ -32,6 +35,7 @@ struct MixedArgs {
     const uint32_t *syn;
     uint32_t *err;
     int32_t *scratch;                      // counts[8], cursors[8], tile counters[8], order[batch]
+    float *hbm_ws;                         // L = 128 messages: [grid][120 * 128]
     int32_t batch;
 };
 
@@ -130,6 +134,57 @@ void k_mix_decode(const MixedArgs m) {
         }
         if (c < 0) return;   // every tile of this pattern and lift size is taken
         mix_tile<S, L>(m, c, first, cnt, lds);
+    }
+}
+
+// Locates tile t of the codes with pattern S::WHICH and lift L (spt shots
+// per tile) by a scalar walk over the bucket order: code c, first index into
+// the order list, shot count; c = -1 once t is past the last tile.
+template <class S, int L, int spt>
+__device__ __forceinline__ void mix_locate(const MixedArgs &m, int t, int &c, int &first, int &cnt) {
+    c = -1;
+    first = cnt = 0;
+    for (int r = 0, acc = 0, tiles = 0; r < m.ncodes; ++r) {
+        int cc = 0;
+        for (int d = 0; d < m.ncodes; ++d)
+            if (m.rank[d] == r) cc = d;
+        const int n = __builtin_amdgcn_readfirstlane(mix::counts(m)[cc]);
+        if (m.L[cc] == L && m.which[cc] == S::WHICH) {
+            const int nt = (n + spt - 1) / spt;
+            if (c < 0 && t < tiles + nt) {
+                c = cc;
+                first = acc + (t - tiles) * spt;
+                cnt = min(spt, n - (t - tiles) * spt);
+            }
+            tiles += nt;
+        }
+        acc += n;
+    }
+}
+
+// Persistent decoder of the L = 128 shots with messages in HBM: each
+// workgroup claims one shot at a time and decodes it in its own workspace
+// slot.  Every value that decides whether a wave reaches a barrier is
+// workgroup-uniform (broadcast through LDS, then readfirstlane).
+template <class S>
+__global__ __launch_bounds__(64 * kMixHbmWaves) void k_mix_hbm(const MixedArgs m) {
+    constexpr int L = 128, NW = kMixHbmWaves;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[HbmLds<S, L, NW>::bytes];
+    __shared__ int tile;
+    float *msg = m.hbm_ws + (long)blockIdx.x * (S::SLOTS * L);
+    for (;;) {
+        if (threadIdx.x == 0) tile = atomicAdd(mix::tile_ctr(m, S::WHICH, L), 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(tile);
+        __syncthreads();   // everyone has read tile before it is claimed again
+        int c, first, cnt;
+        mix_locate<S, L, 1>(m, t, c, first, cnt);
+        if (c < 0) return;   // every L = 128 tile of this pattern is taken
+        const long shot = (long)(int64_t)wave::uniform64((uint64_t)(int64_t)mix::order(m)[first]);
+        const int64_t so = (int64_t)wave::uniform64((uint64_t)m.syn_off[shot]);
+        const int64_t eo = (int64_t)wave::uniform64((uint64_t)m.err_off[shot]);
+        hbm_decode<S, L, 0, NW, false, false>(m.base, m.codes[c], shot, m.syn + so, m.err + eo, msg, lds);
+        __syncthreads();   // LDS reused by the next shot
     }
 }
 
