@@ -47,11 +47,14 @@ def _declare(L):
     L.orc_flood_i8.argtypes = [i32, i32, vp, i32, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, i32]
     L.orc_layered_f32.argtypes = [i32, i32, vp, i32, vp, vp, f32, i32, vp, i32, i32, vp, vp, vp, vp, i32]
     L.orc_layered_i8.argtypes = [i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, i32, i32, vp, vp, vp, vp, i32]
+    L.orc_flood_i16.argtypes = L.orc_flood_i8.argtypes
+    L.orc_layered_i16.argtypes = L.orc_layered_i8.argtypes
     L.orc_nms_forward_f64.argtypes = [i32, i32, vp, i32, vp, vp, vp, i32, vp, vp, i32]
     L.orc_nms_adjoint_f64.argtypes = [i32, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp]
     L.orc_syndrome.argtypes = [i32, i32, vp, i32, vp, vp]
     L.orc_edge_count.argtypes = [i32, i32, vp]
-    for f in ("orc_flood_f32", "orc_flood_i8", "orc_layered_f32", "orc_layered_i8",
+    for f in ("orc_flood_f32", "orc_flood_i8", "orc_layered_f32", "orc_layered_i8", "orc_flood_i16",
+              "orc_layered_i16",
               "orc_nms_forward_f64", "orc_nms_adjoint_f64", "orc_syndrome", "orc_edge_count"):
         getattr(L, f).restype = C.c_int
 
@@ -117,23 +120,37 @@ def alpha_fraction(alpha: float):
     raise ValueError(f"alpha={alpha} is not a dyadic fraction with denominator <= 256")
 
 
-def flood_i8(H, syn, prior_q4, alpha=0.75, max_iters=32, early_stop=True, nthreads=None):
+def _prior_fx(prior, dtype, n):
+    p = np.asarray(prior, dtype=dtype)
+    if p.ndim == 1:
+        p = np.repeat(p[:, None], n, axis=1)
+    return np.ascontiguousarray(p)
+
+
+def _flood_fx(fn, dtype, H, syn, prior, alpha, max_iters, early_stop, nthreads):
     H, syn = _prep(H, syn)
     m, n = H.shape
     B = syn.shape[0]
-    p = np.asarray(prior_q4, dtype=np.int8)
-    if p.ndim == 1:
-        p = np.repeat(p[:, None], n, axis=1)
-    p = np.ascontiguousarray(p)
+    p = _prior_fx(prior, dtype, n)
     num, sh = alpha_fraction(alpha)
     e = np.zeros((B, n), np.uint8)
     conv = np.zeros(B, np.uint8)
     it = np.zeros(B, np.int32)
     Q = np.zeros((B, n), np.float32)
-    rc = lib().orc_flood_i8(m, n, _p(H), B, _p(syn), _p(p), num, sh, int(max_iters),
-                            int(bool(early_stop)), _p(e), _p(conv), _p(it), _p(Q), _threads(nthreads))
+    rc = fn(m, n, _p(H), B, _p(syn), _p(p), num, sh, int(max_iters),
+            int(bool(early_stop)), _p(e), _p(conv), _p(it), _p(Q), _threads(nthreads))
     assert rc == 0
     return Result(e, conv, it, Q)
+
+
+def flood_i8(H, syn, prior_q4, alpha=0.75, max_iters=32, early_stop=True, nthreads=None):
+    """Flooding, int8 messages saturated to [-127, 127], Q4 priors; Q reported as Q/16."""
+    return _flood_fx(lib().orc_flood_i8, np.int8, H, syn, prior_q4, alpha, max_iters, early_stop, nthreads)
+
+
+def flood_i16(H, syn, prior_q8, alpha=0.75, max_iters=32, early_stop=True, nthreads=None):
+    """Flooding, int16 messages saturated to [-32767, 32767], Q8 priors; Q reported as Q/256."""
+    return _flood_fx(lib().orc_flood_i16, np.int16, H, syn, prior_q8, alpha, max_iters, early_stop, nthreads)
 
 
 def _layers(m, layer_size):
@@ -159,25 +176,31 @@ def layered_f32(H, syn, prior, layer_size, alpha=0.75, max_iters=32, early_stop=
     return Result(e, conv, it, Q)
 
 
-def layered_i8(H, syn, prior_q4, layer_size, alpha=0.75, max_iters=32, early_stop=True, nthreads=None):
+def _layered_fx(fn, dtype, H, syn, prior, layer_size, alpha, max_iters, early_stop, nthreads):
     H, syn = _prep(H, syn)
     m, n = H.shape
     B = syn.shape[0]
-    p = np.asarray(prior_q4, dtype=np.int8)
-    if p.ndim == 1:
-        p = np.repeat(p[:, None], n, axis=1)
-    p = np.ascontiguousarray(p)
+    p = _prior_fx(prior, dtype, n)
     num, sh = alpha_fraction(alpha)
     lp = _layers(m, layer_size)
     e = np.zeros((B, n), np.uint8)
     conv = np.zeros(B, np.uint8)
     it = np.zeros(B, np.int32)
     Q = np.zeros((B, n), np.float32)
-    rc = lib().orc_layered_i8(m, n, _p(H), B, _p(syn), _p(p), num, sh, lp.size - 1, _p(lp),
-                              int(max_iters), int(bool(early_stop)), _p(e), _p(conv), _p(it), _p(Q),
-                              _threads(nthreads))
+    rc = fn(m, n, _p(H), B, _p(syn), _p(p), num, sh, lp.size - 1, _p(lp),
+            int(max_iters), int(bool(early_stop)), _p(e), _p(conv), _p(it), _p(Q), _threads(nthreads))
     assert rc == 0
     return Result(e, conv, it, Q)
+
+
+def layered_i8(H, syn, prior_q4, layer_size, alpha=0.75, max_iters=32, early_stop=True, nthreads=None):
+    return _layered_fx(lib().orc_layered_i8, np.int8, H, syn, prior_q4, layer_size, alpha, max_iters,
+                       early_stop, nthreads)
+
+
+def layered_i16(H, syn, prior_q8, layer_size, alpha=0.75, max_iters=32, early_stop=True, nthreads=None):
+    return _layered_fx(lib().orc_layered_i16, np.int16, H, syn, prior_q8, layer_size, alpha, max_iters,
+                       early_stop, nthreads)
 
 
 def nms_forward_f64(H, syn, prior, weights, nthreads=None):

@@ -21,7 +21,12 @@
  *    the outputs are those of iteration I_max;
  *  - floating point: every sum is taken left to right starting from gamma_n
  *    in increasing check index, alpha * min is rounded once, and no fused
- *    multiply-add is allowed (built with -ffp-contract=off).
+ *    multiply-add is allowed (built with -ffp-contract=off);
+ *  - integer formats (the paper's reduced-precision data types, Section 3,
+ *    Table 1: 8- and 16-bit integers): messages saturate symmetrically to
+ *    [-qmax, qmax] (127, or 32767), priors are signed fixed point (Q4 in
+ *    int8, Q8 in int16), alpha = num / 2^sh is applied to the magnitude and
+ *    rounded down before the sign, and every sum is exact in int32.
  *
  * Inside a step the oracle uses the plain definition: for every output edge
  * the excluded minimum, excluded sign product and excluded sum are formed
@@ -150,9 +155,10 @@ static void cn_f64(const graph_t *g, int r, int s_bit, const double *q, double *
     }
 }
 
-/* int8 check rule: magnitudes are |q| in [0, 127]; alpha = num / 2^sh is  */
-/* applied to the magnitude and rounded down, before the sign.             */
-static void cn_i8(const graph_t *g, int r, int s_bit, const int *q, int *rout, int num, int sh) {
+/* Fixed-point check rule (int8 and int16 messages): magnitudes are |q| in  */
+/* [0, qmax]; alpha = num / 2^sh is applied to the magnitude and rounded    */
+/* down, before the sign.                                                   */
+static void cn_fx(const graph_t *g, int r, int s_bit, const int *q, int *rout, int num, int sh) {
     int lo = g->row_ptr[r], hi = g->row_ptr[r + 1];
     for (int i = lo; i < hi; i++) {
         int mag = 1 << 30;
@@ -168,7 +174,20 @@ static void cn_i8(const graph_t *g, int r, int s_bit, const int *q, int *rout, i
     }
 }
 
-static inline int clamp127(int x) { return x > 127 ? 127 : (x < -127 ? -127 : x); }
+static inline int clampq(int x, int qmax) { return x > qmax ? qmax : (x < -qmax ? -qmax : x); }
+
+/* Fixed-point formats.  Messages saturate symmetrically to [-qmax, qmax];  */
+/* priors are signed fixed point with `frac` fraction bits, held in        */
+/* `bits`-bit integers; the reported posterior is Q / 2^frac.              */
+/*   int8:  qmax = 127,   Q4 priors (frac = 4);                            */
+/*   int16: qmax = 32767, Q8 priors (frac = 8).                            */
+typedef struct { int bits, qmax, frac; } fxfmt_t;
+static const fxfmt_t FX_I8 = {8, 127, 4};
+static const fxfmt_t FX_I16 = {16, 32767, 8};
+
+static inline int prior_at(const void *p, fxfmt_t f, long i) {
+    return f.bits == 8 ? (int)((const int8_t *)p)[i] : (int)((const int16_t *)p)[i];
+}
 
 /* ---------------------------------------------------------------------- */
 /* Flooding schedule, FP32 (Algorithm 1).  Optional per-iteration weights   */
@@ -231,35 +250,36 @@ int orc_flood_f32(int m, int n, const uint8_t *H, int nshots,
     return 0;
 }
 
-/* Flooding, int8 messages.  q and r live in [-127, 127]; sums are exact   */
-/* int32 and saturate only where a message is formed.                      */
-int orc_flood_i8(int m, int n, const uint8_t *H, int nshots,
-                 const uint8_t *syn, const int8_t *prior_q4, int alpha_num, int alpha_shift,
-                 int max_iters, int early_stop,
-                 uint8_t *e_out, uint8_t *conv, int32_t *iters, float *Q_out, int nthreads) {
+/* Flooding, fixed-point messages.  q and r live in [-qmax, qmax]; sums    */
+/* are exact int32 and saturate only where a message is formed.            */
+static int flood_fx(int m, int n, const uint8_t *H, int nshots,
+                    const uint8_t *syn, const void *prior, fxfmt_t f, int alpha_num, int alpha_shift,
+                    int max_iters, int early_stop,
+                    uint8_t *e_out, uint8_t *conv, int32_t *iters, float *Q_out, int nthreads) {
     graph_t g;
     if (graph_build(&g, m, n, H)) return -1;
     int nnz = g.nnz;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
     for (int b = 0; b < nshots; b++) {
         const uint8_t *s = syn + (long)b * m;
-        const int8_t *gam = prior_q4 + (long)b * n;
         uint8_t *e = e_out + (long)b * n;
         int *q = malloc(sizeof(int) * (nnz + 1));
         int *rr = malloc(sizeof(int) * (nnz + 1));
         int *Q = malloc(sizeof(int) * (n + 1));
+        int *gam = malloc(sizeof(int) * (n + 1));
+        for (int c = 0; c < n; c++) gam[c] = prior_at(prior, f, (long)b * n + c);
         for (int c = 0; c < n; c++)
             for (int k = g.vn_ptr[c]; k < g.vn_ptr[c + 1]; k++) q[g.vn_edge[k]] = gam[c];
         int done = 0, k;
         for (k = 1; k <= max_iters; k++) {
-            for (int r = 0; r < m; r++) cn_i8(&g, r, s[r] & 1, q, rr, alpha_num, alpha_shift);
+            for (int r = 0; r < m; r++) cn_fx(&g, r, s[r] & 1, q, rr, alpha_num, alpha_shift);
             for (int c = 0; c < n; c++) {
                 int lo = g.vn_ptr[c], hi = g.vn_ptr[c + 1];
                 for (int i = lo; i < hi; i++) {
                     int acc = gam[c];
                     for (int j = lo; j < hi; j++)
                         if (j != i) acc += rr[g.vn_edge[j]];
-                    q[g.vn_edge[i]] = clamp127(acc);
+                    q[g.vn_edge[i]] = clampq(acc, f.qmax);
                 }
                 int acc = gam[c];
                 for (int j = lo; j < hi; j++) acc += rr[g.vn_edge[j]];
@@ -271,11 +291,27 @@ int orc_flood_i8(int m, int n, const uint8_t *H, int nshots,
         if (done) { conv[b] = 1; iters[b] = k; }
         else { conv[b] = (uint8_t)syndrome_matches(&g, e, s); iters[b] = max_iters; }
         if (Q_out)
-            for (int c = 0; c < n; c++) Q_out[(long)b * n + c] = (float)Q[c] / 16.0f;
-        free(q); free(rr); free(Q);
+            for (int c = 0; c < n; c++) Q_out[(long)b * n + c] = (float)Q[c] / (float)(1 << f.frac);
+        free(q); free(rr); free(Q); free(gam);
     }
     graph_free(&g);
     return 0;
+}
+
+int orc_flood_i8(int m, int n, const uint8_t *H, int nshots,
+                 const uint8_t *syn, const int8_t *prior_q4, int alpha_num, int alpha_shift,
+                 int max_iters, int early_stop,
+                 uint8_t *e_out, uint8_t *conv, int32_t *iters, float *Q_out, int nthreads) {
+    return flood_fx(m, n, H, nshots, syn, prior_q4, FX_I8, alpha_num, alpha_shift, max_iters,
+                    early_stop, e_out, conv, iters, Q_out, nthreads);
+}
+
+int orc_flood_i16(int m, int n, const uint8_t *H, int nshots,
+                  const uint8_t *syn, const int16_t *prior_q8, int alpha_num, int alpha_shift,
+                  int max_iters, int early_stop,
+                  uint8_t *e_out, uint8_t *conv, int32_t *iters, float *Q_out, int nthreads) {
+    return flood_fx(m, n, H, nshots, syn, prior_q8, FX_I16, alpha_num, alpha_shift, max_iters,
+                    early_stop, e_out, conv, iters, Q_out, nthreads);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -285,10 +321,10 @@ int orc_flood_i8(int m, int n, const uint8_t *H, int nshots,
 /* Per check: q_e = Q_n - r_e, new r from those q as in the check rule,     */
 /* then Q_n = q_e + r_new_e.  One sweep over all layers is one iteration,   */
 /* followed by the decision and the syndrome test.  Starting state: Q =     */
-/* gamma, r = 0.  int8: the check rule reads the saturated message          */
-/* q_e = clamp(Q_n - r_e, -127, 127), while the posterior is updated        */
+/* gamma, r = 0.  Fixed point: the check rule reads the saturated message  */
+/* q_e = clamp(Q_n - r_e, -qmax, qmax), while the posterior is updated      */
 /* exactly, Q_n = (Q_n - r_e) + r_new_e, so Q_n = gamma_n + sum of the      */
-/* current r of its checks at all times (|Q_n| <= 127 + d_v * 95).          */
+/* current r of its checks at all times (|Q_n| <= qmax + d_v * alpha qmax). */
 /* ---------------------------------------------------------------------- */
 int orc_layered_f32(int m, int n, const uint8_t *H, int nshots,
                     const uint8_t *syn, const float *prior, float alpha,
@@ -331,33 +367,32 @@ int orc_layered_f32(int m, int n, const uint8_t *H, int nshots,
     return 0;
 }
 
-int orc_layered_i8(int m, int n, const uint8_t *H, int nshots,
-                   const uint8_t *syn, const int8_t *prior_q4, int alpha_num, int alpha_shift,
-                   int nlayers, const int32_t *layer_ptr, int max_iters, int early_stop,
-                   uint8_t *e_out, uint8_t *conv, int32_t *iters, float *Q_out, int nthreads) {
+static int layered_fx(int m, int n, const uint8_t *H, int nshots,
+                      const uint8_t *syn, const void *prior, fxfmt_t f, int alpha_num, int alpha_shift,
+                      int nlayers, const int32_t *layer_ptr, int max_iters, int early_stop,
+                      uint8_t *e_out, uint8_t *conv, int32_t *iters, float *Q_out, int nthreads) {
     graph_t g;
     if (graph_build(&g, m, n, H)) return -1;
     int nnz = g.nnz;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
     for (int b = 0; b < nshots; b++) {
         const uint8_t *s = syn + (long)b * m;
-        const int8_t *gam = prior_q4 + (long)b * n;
         uint8_t *e = e_out + (long)b * n;
         int *rr = calloc((size_t)nnz + 1, sizeof(int));
         int *qloc = malloc(sizeof(int) * (nnz + 1));
         int *rnew = malloc(sizeof(int) * (nnz + 1));
         int *Q = malloc(sizeof(int) * (n + 1));
-        for (int c = 0; c < n; c++) Q[c] = gam[c];
+        for (int c = 0; c < n; c++) Q[c] = prior_at(prior, f, (long)b * n + c);
         int done = 0, k;
         for (k = 1; k <= max_iters; k++) {
             for (int l = 0; l < nlayers; l++)
                 for (int r = layer_ptr[l]; r < layer_ptr[l + 1]; r++) {
                     int lo = g.row_ptr[r], hi = g.row_ptr[r + 1];
-                    for (int f = lo; f < hi; f++) qloc[f] = clamp127(Q[g.col[f]] - rr[f]);
-                    cn_i8(&g, r, s[r] & 1, qloc, rnew, alpha_num, alpha_shift);
-                    for (int f = lo; f < hi; f++) {
-                        Q[g.col[f]] = (Q[g.col[f]] - rr[f]) + rnew[f];
-                        rr[f] = rnew[f];
+                    for (int x = lo; x < hi; x++) qloc[x] = clampq(Q[g.col[x]] - rr[x], f.qmax);
+                    cn_fx(&g, r, s[r] & 1, qloc, rnew, alpha_num, alpha_shift);
+                    for (int x = lo; x < hi; x++) {
+                        Q[g.col[x]] = (Q[g.col[x]] - rr[x]) + rnew[x];
+                        rr[x] = rnew[x];
                     }
                 }
             for (int c = 0; c < n; c++) e[c] = Q[c] < 0 ? 1 : 0;
@@ -366,11 +401,27 @@ int orc_layered_i8(int m, int n, const uint8_t *H, int nshots,
         if (done) { conv[b] = 1; iters[b] = k; }
         else { conv[b] = (uint8_t)syndrome_matches(&g, e, s); iters[b] = max_iters; }
         if (Q_out)
-            for (int c = 0; c < n; c++) Q_out[(long)b * n + c] = (float)Q[c] / 16.0f;
+            for (int c = 0; c < n; c++) Q_out[(long)b * n + c] = (float)Q[c] / (float)(1 << f.frac);
         free(rr); free(qloc); free(rnew); free(Q);
     }
     graph_free(&g);
     return 0;
+}
+
+int orc_layered_i8(int m, int n, const uint8_t *H, int nshots,
+                   const uint8_t *syn, const int8_t *prior_q4, int alpha_num, int alpha_shift,
+                   int nlayers, const int32_t *layer_ptr, int max_iters, int early_stop,
+                   uint8_t *e_out, uint8_t *conv, int32_t *iters, float *Q_out, int nthreads) {
+    return layered_fx(m, n, H, nshots, syn, prior_q4, FX_I8, alpha_num, alpha_shift, nlayers, layer_ptr,
+                      max_iters, early_stop, e_out, conv, iters, Q_out, nthreads);
+}
+
+int orc_layered_i16(int m, int n, const uint8_t *H, int nshots,
+                    const uint8_t *syn, const int16_t *prior_q8, int alpha_num, int alpha_shift,
+                    int nlayers, const int32_t *layer_ptr, int max_iters, int early_stop,
+                    uint8_t *e_out, uint8_t *conv, int32_t *iters, float *Q_out, int nthreads) {
+    return layered_fx(m, n, H, nshots, syn, prior_q8, FX_I16, alpha_num, alpha_shift, nlayers, layer_ptr,
+                      max_iters, early_stop, e_out, conv, iters, Q_out, nthreads);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -3,16 +3,19 @@
 * Equation (PCM) of Section 2: adjacency sets and degrees as printed.
 * Tree-shaped Tanner graphs: with alpha = 1 and enough iterations min-sum is
   exact max-product, so Q_n = gamma (W_1(n) - W_0(n)) with W_b from brute
-  force (flooding and layered, FP32 and int8).
+  force (flooding and layered, FP32, int8 and int16).
 * Closed form of the first iteration under a uniform prior (Algorithm 1
-  check rule, then the a-posteriori sum), FP32 and int8, including per-edge
-  neural weights indexed by row-major edge position.
+  check rule, then the a-posteriori sum), FP32, int8 and int16, including
+  per-edge neural weights indexed by row-major edge position.
+* Saturation closed form of the fixed-point formats: with s = 0 and a large
+  prior every message saturates at its bound, so from the second iteration on
+  Q_n = gamma_q + d_v(n) ((3 qmax) >> 2), exactly.
 * Exact scale invariance gamma -> 2 gamma (FP32).
 * Stopping rule: the reported iteration is the first k with H e^(k) = s,
   converged outputs reproduce the syndrome (checked by an independent
   GF(2) product), inconsistent syndromes never converge.
 * Brute-force minimum-weight decoding on tiny loopy codes.
-* int8 flooding against an independent numpy decoder in the
+* int8 and int16 flooding against an independent numpy decoder in the
   (min1, min2, Q - r) form, which is exact in integers.
 * Neural min-sum: weights all equal to alpha reproduce alpha-MS bit for bit;
   the float64 adjoint matches central finite differences.
@@ -113,6 +116,13 @@ def test_tree_exact_max_product_flood_and_layered(seed):
     rl8 = oracle.layered_i8(H, s[None], np.full(n, gq, np.int8)[None], 1, alpha=1.0, max_iters=iters,
                             early_stop=False)
     assert np.array_equal(rl8.Q[0] * 16, (gq * (W[1] - W[0])).astype(np.float32))
+    # int16 with a Q8 prior beyond the int8 range: Q = gq (W1 - W0) / 256
+    gq16 = 700
+    p16 = np.full(n, gq16, np.int16)[None]
+    r16 = oracle.flood_i16(H, s[None], p16, alpha=1.0, max_iters=iters, early_stop=False)
+    assert np.array_equal(r16.Q[0] * 256, (gq16 * (W[1] - W[0])).astype(np.float32))
+    rl16 = oracle.layered_i16(H, s[None], p16, 1, alpha=1.0, max_iters=iters, early_stop=False)
+    assert np.array_equal(rl16.Q[0] * 256, (gq16 * (W[1] - W[0])).astype(np.float32))
     # the hard decision of exact max-product is a minimum-weight solution when unique
     e_min, w_min = oracle.min_weight_decode(H, s)
     if np.all(want != 0):
@@ -163,6 +173,38 @@ def test_first_iteration_closed_form_int8():
         assert np.array_equal(r.Q[sh] * 16, want.astype(np.float32))
 
 
+def test_first_iteration_closed_form_int16():
+    c = lp.lp_code(16)
+    H = c.hz.dense()
+    b = noise.Batch(c.hz, 6, np.arange(4), 0.03)
+    gq = int(b.gamma_q8()[0])
+    assert gq == 890          # round(256 * log(0.97 / 0.03)) = round(889.9)
+    r = oracle.flood_i16(H, b.s, np.full(4, gq, np.int16), max_iters=1, early_stop=False)
+    mag = (3 * gq) >> 2
+    for sh in range(4):
+        want = gq + np.array([sum(-mag if b.s[sh, mm] else mag for mm in np.nonzero(H[:, nn])[0])
+                              for nn in range(c.n)])
+        assert np.array_equal(r.Q[sh] * 256, want.astype(np.float32))
+
+
+@pytest.mark.parametrize("fmt", ["i8", "i16"])
+def test_fixed_point_saturation_closed_form(fmt):
+    # s = 0, uniform prior g near the bound: after iteration 1 every excluded
+    # sum g + (d-1) r exceeds qmax (d >= 2), so every q is qmax, every r is
+    # (3 qmax) >> 2 and Q_n = g + d_v(n) ((3 qmax) >> 2) from then on.
+    c = lp.lp_code(16)
+    H = c.hz.dense()
+    s = np.zeros((2, c.hz.m), np.uint8)
+    qmax, g, dt, run, scale = {
+        "i8": (127, 120, np.int8, oracle.flood_i8, 16),
+        "i16": (32767, 30000, np.int16, oracle.flood_i16, 256)}[fmt]
+    dv = H.sum(0).astype(np.int64)
+    for k in (2, 3):
+        r = run(H, s, np.full(2, g, dt), max_iters=k, early_stop=False)
+        want = (g + dv * ((3 * qmax) >> 2)).astype(np.float32)
+        assert np.array_equal(r.Q[0] * scale, want) and np.array_equal(r.Q[1] * scale, want)
+
+
 def test_scale_invariance_fp32():
     c = lp.lp_code(16)
     H = c.hz.dense()
@@ -179,7 +221,7 @@ def test_scale_invariance_fp32():
     assert np.array_equal(r4.e, r1b.e) and np.array_equal(r4.iters, r1b.iters)
 
 
-@pytest.mark.parametrize("fmt", ["f32", "i8", "lf32", "li8"])
+@pytest.mark.parametrize("fmt", ["f32", "i8", "i16", "lf32", "li8", "li16"])
 def test_stopping_rule_and_convergence(fmt):
     c = lp.lp_code(16)
     H = c.hz.dense()
@@ -189,6 +231,8 @@ def test_stopping_rule_and_convergence(fmt):
         "i8": lambda **k: oracle.flood_i8(H, b.s, b.gamma_q4(), **k),
         "lf32": lambda **k: oracle.layered_f32(H, b.s, b.gamma, 16, **k),
         "li8": lambda **k: oracle.layered_i8(H, b.s, b.gamma_q4(), 16, **k),
+        "i16": lambda **k: oracle.flood_i16(H, b.s, b.gamma_q8(), **k),
+        "li16": lambda **k: oracle.layered_i16(H, b.s, b.gamma_q8(), 16, **k),
     }[fmt]
     r = run(max_iters=32)
     ok = r.converged == 1
@@ -227,6 +271,8 @@ def test_zero_syndrome_returns_zero_at_first_iteration():
     H = c.hz.dense()
     s = np.zeros((3, c.hz.m), np.uint8)
     for r in (oracle.flood_f32(H, s, np.float32(2.0)), oracle.flood_i8(H, s, np.full(3, 40, np.int8)),
+              oracle.flood_i16(H, s, np.full(3, 640, np.int16)),
+              oracle.layered_i16(H, s, np.full(3, 640, np.int16), 16),
               oracle.layered_f32(H, s, np.float32(2.0), 16)):
         assert np.all(r.iters == 1) and np.all(r.converged == 1) and not r.e.any()
 
@@ -249,8 +295,8 @@ def test_tiny_loopy_codes_against_brute_force(seed):
             assert r.e[i].sum() >= wmin
 
 
-def _numpy_i8_flood(H, s, gq, max_iters, anum=3, ash=2):
-    """Independent int8 flooding in the (min1, min2, Q - r) form."""
+def _numpy_fx_flood(H, s, gq, max_iters, qmax, anum=3, ash=2):
+    """Independent fixed-point flooding in the (min1, min2, Q - r) form."""
     m, n = H.shape
     rows = [np.nonzero(H[i])[0] for i in range(m)]
     B = s.shape[0]
@@ -262,7 +308,7 @@ def _numpy_i8_flood(H, s, gq, max_iters, anum=3, ash=2):
         for k in range(1, max_iters + 1):
             newr = []
             for i, c in enumerate(rows):
-                q = np.clip(Q[c] - r[i], -127, 127)
+                q = np.clip(Q[c] - r[i], -qmax, qmax)
                 a = np.abs(q)
                 o = np.argsort(a, kind="stable")
                 m1, m2 = a[o[0]], a[o[1]]
@@ -282,13 +328,16 @@ def _numpy_i8_flood(H, s, gq, max_iters, anum=3, ash=2):
     return out_e, out_it
 
 
-def test_int8_against_independent_q_minus_r_form():
+@pytest.mark.parametrize("fmt", ["i8", "i16"])
+def test_fixed_point_against_independent_q_minus_r_form(fmt):
     c = lp.lp_code(16)
     H = c.hz.dense()
     b = noise.Batch(c.hz, 12, np.arange(24), 0.05)
-    gq = b.gamma_q4()
-    r = oracle.flood_i8(H, b.s, gq, max_iters=12)
-    e, it = _numpy_i8_flood(H, b.s, gq, 12)
+    if fmt == "i8":
+        gq, qmax, r = b.gamma_q4(), 127, oracle.flood_i8(H, b.s, b.gamma_q4(), max_iters=12)
+    else:
+        gq, qmax, r = b.gamma_q8(), 32767, oracle.flood_i16(H, b.s, b.gamma_q8(), max_iters=12)
+    e, it = _numpy_fx_flood(H, b.s, gq, 12, qmax)
     assert np.array_equal(r.e, e) and np.array_equal(r.iters, it)
 
 

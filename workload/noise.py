@@ -5,7 +5,9 @@ probability p, e_n = [u(seed, shot, n) < p].  The syndrome the decoder sees
 is s = H_Z e^T over GF(2) (Section 2).  The per-bit prior of normalized
 min-sum is the log-likelihood ratio gamma = log((1 - p) / p), rounded once to
 float32.  The int8 format carries priors as signed Q4 fixed point:
-round-half-away-from-zero(16 * gamma) clamped to [-127, 127].
+round-half-away-from-zero(16 * gamma) clamped to [-127, 127]; the int16
+format as signed Q8: round-half-away-from-zero(256 * gamma) clamped to
+[-32767, 32767].
 
 Nothing here decodes; these are inputs shared by the oracle and the device
 path.
@@ -67,6 +69,16 @@ def quantize_q4(gamma) -> np.ndarray:
     return np.clip(r, -127, 127).astype(np.int8)
 
 
+def quantize_q8(gamma) -> np.ndarray:
+    """int16 Q8 prior: clamp(round-half-away(256 * gamma), -32767, 32767).
+
+    256 * gamma is exact in float32, so the only rounding is the final one.
+    """
+    g = np.asarray(gamma, dtype=np.float32) * np.float32(256.0)
+    r = np.sign(g) * np.floor(np.abs(g).astype(np.float64) + 0.5)
+    return np.clip(r, -32767, 32767).astype(np.int16)
+
+
 def shot_rates(seed: int, shots, lo: float = 0.01, hi: float = 0.08) -> np.ndarray:
     """Per-shot noise rate p ~ U[lo, hi)."""
     u = rng.uniform(seed, rng.DOMAIN_PSHOT, np.asarray(shots), 0)
@@ -108,6 +120,9 @@ class Batch:
 
     def gamma_q4(self) -> np.ndarray:
         return quantize_q4(self.gamma)
+
+    def gamma_q8(self) -> np.ndarray:
+        return quantize_q8(self.gamma)
 
     def prior_bits(self) -> np.ndarray:
         """float32 [B, n]: the per-shot prior broadcast to every bit."""
