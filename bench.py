@@ -106,7 +106,8 @@ def main():
         syn = torch.from_numpy(bits.pack_bits(b.s).view(np.int32)).to(dev)
         g32 = torch.from_numpy(b.gamma).to(dev)
         g8 = torch.from_numpy(b.gamma_q4()).to(dev)
-        batches.append(dict(p=p, batch=b, syn=syn, g32=g32, g8=g8, out=dec.outputs(B)))
+        g16 = torch.from_numpy(b.gamma_q8()).to(dev)
+        batches.append(dict(p=p, batch=b, syn=syn, g32=g32, g8=g8, g16=g16, out=dec.outputs(B)))
     gen_s = time.time() - t0
 
     stream = torch.cuda.current_stream()
@@ -114,7 +115,7 @@ def main():
     def run(fmt, sched, timed_events=None, layout=abi.QLDPC_LAYOUT_WAVE):
         prm = dec.params(fmt=fmt, sched=sched, max_iters=32, early_stop=True, layout=layout)
         for j, bb in enumerate(batches):
-            pr = bb["g32"] if fmt == abi.QLDPC_F32 else bb["g8"]
+            pr = {abi.QLDPC_F32: bb["g32"], abi.QLDPC_I8Q4: bb["g8"], abi.QLDPC_I16Q8: bb["g16"]}[fmt]
             if timed_events is not None:
                 timed_events[j][0].record(stream)
             abi.qldpc_decode_batch(dec.handle, prm, B, bb["syn"], pr, *bb["out"][:3], None, stream)
@@ -212,7 +213,9 @@ def main():
         R_ = RG if args.L <= 64 else W
         for name, fmt, sched, bpm, lay in (("f32_flood_lds_layout", 0, 0, 4, W), ("int8_flood", 1, 0, 1, R_),
                                            ("f32_layered", 0, 1, 4, R_), ("f32_layered_lds_layout", 0, 1, 4, W),
-                                           ("int8_layered", 1, 1, 1, R_)):
+                                           ("int8_layered", 1, 1, 1, R_), ("int16_flood", 2, 0, 2, R_),
+                                           ("int16_layered", 2, 1, 2, R_), ("int16_flood_lds_layout", 2, 0, 2, W),
+                                           ("int8_flood_lds_layout", 1, 0, 1, W)):
             w, k_, it_ = measure(fmt, sched, max(3, args.steps // 4), 1, layout=lay)
             st = max(3, args.steps // 4)
             variants[name] = dict(

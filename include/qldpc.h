@@ -104,9 +104,16 @@ qldpc_status qldpc_code_info(qldpc_code code, int32_t *m, int32_t *n, int32_t *n
 
 typedef enum {
     QLDPC_F32 = 0,   /* FP32 messages; priors are float LLRs                 */
-    QLDPC_I8Q4 = 1   /* int8 saturating messages in [-127, 127]; priors are
+    QLDPC_I8Q4 = 1,  /* int8 saturating messages in [-127, 127]; priors are
                         int8 Q4 fixed point (LLR * 16, see
                         qldpc_quantize_prior); alpha must be num / 2^sh       */
+    QLDPC_I16Q8 = 2  /* int16 saturating messages in [-32767, 32767]; priors
+                        are int16 Q8 fixed point (LLR * 256, see
+                        qldpc_quantize_prior_q8); alpha must be num / 2^sh.
+                        The 8- and 16-bit integer data types are the paper's
+                        reduced-precision formats (Section 3, Table 1).  Every
+                        layout, lift and pattern supports it; sums are exact
+                        in 32-bit integers.                                   */
 } qldpc_format;
 
 typedef enum {
@@ -160,12 +167,13 @@ void qldpc_default_params(qldpc_decode_params *p);
 
 /* Decodes `batch` syndromes of one code.
  *   syndromes  device uint32 [batch][ceil(m/32)]
- *   priors     device float [batch] or [batch][n] (F32), int8 likewise (I8Q4)
+ *   priors     device float [batch] or [batch][n] (F32), int8 likewise (I8Q4),
+ *              int16 likewise (I16Q8)
  *   errors     device uint32 [batch][ceil(n/32)], out: e_hat
  *   converged  device uint8 [batch], out: 1 iff H e_hat = s at exit
  *   iters_used device uint8 [batch], out, may be NULL: iterations executed
  *   posterior  device float [batch][n], out, may be NULL: a-posteriori LLR Q
- *              of the returned iteration (I8Q4: Q / 16)
+ *              of the returned iteration (I8Q4: Q / 16; I16Q8: Q / 256)
  * For each shot, the iteration k whose decision is returned is the first
  * with H e^(k) = s when early_stop is set, else max_iters.  batch = 0 is a
  * no-op.  Errors: INVALID_ARG, UNSUPPORTED (format/schedule/layout
@@ -177,7 +185,7 @@ qldpc_status qldpc_decode_batch(qldpc_code code, const qldpc_decode_params *para
 
 /* Device bytes of message workspace a decode of `batch` shots with these
  * parameters needs when called through qldpc_decode_batch_ws: batch * 120
- * * L * (4 for F32, 1 for I8Q4) when the chosen layout keeps messages in
+ * * L * (4 for F32, 1 for I8Q4, 2 for I16Q8) when the chosen layout keeps messages in
  * device memory (QLDPC_LAYOUT_HBM; see its AUTO rule), else 0.  Errors as
  * qldpc_decode_batch. */
 qldpc_status qldpc_decode_workspace_bytes(qldpc_code code, const qldpc_decode_params *params, int32_t batch,
@@ -446,6 +454,10 @@ qldpc_status qldpc_server_loadgen(qldpc_server srv, const qldpc_loadgen_config *
 /* Host helper: int8 Q4 prior clamp(round-half-away-from-zero(16 * llr),
  * -127, 127) for `count` values (host arrays). */
 qldpc_status qldpc_quantize_prior(const float *llr, int8_t *out, int64_t count);
+
+/* Host helper: int16 Q8 prior clamp(round-half-away-from-zero(256 * llr),
+ * -32767, 32767) for `count` values (host arrays). */
+qldpc_status qldpc_quantize_prior_q8(const float *llr, int16_t *out, int64_t count);
 
 #ifdef __cplusplus
 }

@@ -63,7 +63,7 @@ class Decoder:
         return err, conv, it, post
 
     def decode(self, syndromes, priors, params=None, posterior: bool = False, out=None, stream=None):
-        """syndromes: int32 [B, ceil(m/32)] packed; priors: float32 or int8,
+        """syndromes: int32 [B, ceil(m/32)] packed; priors: float32, int8 or int16,
         [B] or [B, n].  Returns (errors int32 [B, ceil(n/32)], converged u8,
         iterations u8, posterior or None)."""
         params = params or self.params()

@@ -23,7 +23,7 @@ QLDPC_ERR_DEVICE = 4
 QLDPC_ERR_CAPACITY = 5
 QLDPC_ERR_NOT_READY = 6
 
-QLDPC_F32, QLDPC_I8Q4 = 0, 1
+QLDPC_F32, QLDPC_I8Q4, QLDPC_I16Q8 = 0, 1, 2
 QLDPC_FLOOD, QLDPC_LAYERED = 0, 1
 QLDPC_PRIOR_PER_SHOT, QLDPC_PRIOR_PER_BIT = 0, 1
 QLDPC_LAYOUT_AUTO, QLDPC_LAYOUT_WAVE, QLDPC_LAYOUT_BLOCK, QLDPC_LAYOUT_WAVE_REG, QLDPC_LAYOUT_HBM = 0, 1, 2, 3, 4
@@ -94,6 +94,7 @@ def _load():
         "qldpc_version": ([], i32),
         "qldpc_default_params": ([C.POINTER(qldpc_decode_params)], None),
         "qldpc_quantize_prior": ([vp, vp, i64], i32),
+        "qldpc_quantize_prior_q8": ([vp, vp, i64], i32),
         "qldpc_code_create": ([C.POINTER(qldpc_code_desc), i32, C.POINTER(vp)], i32),
         "qldpc_code_destroy": ([vp], i32),
         "qldpc_code_info": ([vp, vp, vp, vp, vp, vp], i32),
@@ -171,6 +172,14 @@ def qldpc_quantize_prior(llr: np.ndarray) -> np.ndarray:
     x = np.ascontiguousarray(llr, dtype=np.float32)
     out = np.empty(x.shape, np.int8)
     _check(lib.qldpc_quantize_prior(x.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), x.size))
+    return out
+
+
+def qldpc_quantize_prior_q8(llr: np.ndarray) -> np.ndarray:
+    """int16 Q8 priors: clamp(round-half-away(256 * llr), -32767, 32767)."""
+    x = np.ascontiguousarray(llr, dtype=np.float32)
+    out = np.empty(x.shape, np.int16)
+    _check(lib.qldpc_quantize_prior_q8(x.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), x.size))
     return out
 
 

@@ -49,7 +49,8 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     if (batch < 0) return fail(QLDPC_ERR_INVALID_ARG, "decode: negative batch");
     if (p->max_iters < 1 || p->max_iters > 255)
         return fail(QLDPC_ERR_INVALID_ARG, "decode: max_iters must be in [1, 255]");
-    if (p->fmt != QLDPC_F32 && p->fmt != QLDPC_I8Q4) return fail(QLDPC_ERR_INVALID_ARG, "decode: bad format");
+    if (p->fmt != QLDPC_F32 && p->fmt != QLDPC_I8Q4 && p->fmt != QLDPC_I16Q8)
+        return fail(QLDPC_ERR_INVALID_ARG, "decode: bad format");
     if (p->sched != QLDPC_FLOOD && p->sched != QLDPC_LAYERED)
         return fail(QLDPC_ERR_INVALID_ARG, "decode: bad schedule");
     if (p->prior_mode != QLDPC_PRIOR_PER_SHOT && p->prior_mode != QLDPC_PRIOR_PER_BIT)
@@ -65,13 +66,13 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     a->max_iters = p->max_iters;
     a->early_stop = p->early_stop ? 1 : 0;
     a->alpha = p->alpha;
-    if (p->fmt == QLDPC_I8Q4) {
+    if (p->fmt != QLDPC_F32) {
         int sh = 0;
         for (; sh <= 8; ++sh) {
             const float num = p->alpha * (float)(1 << sh);
             if (num == std::floor(num)) break;
         }
-        if (sh > 8) return fail(QLDPC_ERR_UNSUPPORTED, "decode: int8 needs alpha = num / 2^s, s <= 8");
+        if (sh > 8) return fail(QLDPC_ERR_UNSUPPORTED, "decode: integer formats need alpha = num / 2^s, s <= 8");
         a->alpha_num = (int32_t)(p->alpha * (float)(1 << sh));
         a->alpha_shift = sh;
     }
@@ -152,6 +153,20 @@ qldpc_status qldpc_quantize_prior(const float *llr, int8_t *out, int64_t count) 
         if (r > 127) r = 127;
         if (r < -127) r = -127;
         out[i] = (int8_t)r;
+    }
+    return QLDPC_OK;
+}
+
+qldpc_status qldpc_quantize_prior_q8(const float *llr, int16_t *out, int64_t count) {
+    if (count < 0 || (count > 0 && (!llr || !out)))
+        return fail(QLDPC_ERR_INVALID_ARG, "quantize_prior_q8: bad arguments");
+    for (int64_t i = 0; i < count; ++i) {
+        const float v = llr[i] * 256.0f;   // exact: scaling by a power of two
+        double r = std::floor(std::fabs((double)v) + 0.5);
+        if (v < 0) r = -r;
+        if (r > 32767) r = 32767;
+        if (r < -32767) r = -32767;
+        out[i] = (int16_t)r;
     }
     return QLDPC_OK;
 }
@@ -289,7 +304,8 @@ namespace {
 // Bytes of message workspace for key k and `batch` shots (0 when on chip).
 size_t workspace_bytes_for(const qldpc_code code, const LaunchKey &k, int32_t batch) {
     if (k.layout != QLDPC_LAYOUT_HBM) return 0;
-    return (size_t)batch * 120 * (size_t)code->L * (k.fmt == QLDPC_F32 ? 4 : 1);
+    const size_t bytes_per_msg = k.fmt == QLDPC_F32 ? 4 : k.fmt == QLDPC_I16Q8 ? 2 : 1;
+    return (size_t)batch * 120 * (size_t)code->L * bytes_per_msg;
 }
 
 qldpc_status decode_impl(qldpc_code code, const qldpc_decode_params *p, int32_t batch, const uint32_t *syn,

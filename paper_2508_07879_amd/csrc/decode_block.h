@@ -170,7 +170,7 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const long sho
                     acc_t Q = Qr[Plan::P.slot[it]];
                     float qv;
                     if constexpr (FMT == 0) qv = Q;
-                    else qv = (float)Q * 0.0625f;
+                    else qv = (float)Q * Fmt<FMT>::post_scale;
                     a.post[shot * N + C * L + lane + 64 * h] = qv;
                 }
             });
@@ -224,7 +224,7 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const long sho
                     int v[DC];
 #pragma unroll
                     for (int j = 0; j < DC; ++j) v[j] = msg[(R * DC + j) * L + lane + 64 * h];
-                    cn_i8<DC>(v, P, a.alpha_num, a.alpha_shift);
+                    cn_fx<DC>(v, P, a.alpha_num, a.alpha_shift);
 #pragma unroll
                     for (int j = 0; j < DC; ++j) msg[(R * DC + j) * L + lane + 64 * h] = (msg_t)v[j];
                 }
@@ -269,7 +269,7 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const long sho
 #pragma unroll
                     for (int i = 0; i < d; ++i) sum += r[i];
 #pragma unroll
-                    for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
+                    for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat<FMT>(sum - r[i]);
                     Q = sum;
                 }
                 if constexpr (POST) Qr[Plan::P.slot[it]] = Q;

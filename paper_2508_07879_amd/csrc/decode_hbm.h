@@ -152,7 +152,7 @@ __device__ __forceinline__ void hbm_decode(const DecodeArgs &a, const DevCode *c
                 int v[DC];
 #pragma unroll
                 for (int j = 0; j < DC; ++j) v[j] = row[j * L];
-                cn_i8<DC>(v, P, a.alpha_num, a.alpha_shift);
+                cn_fx<DC>(v, P, a.alpha_num, a.alpha_shift);
 #pragma unroll
                 for (int j = 0; j < DC; ++j) row[j * L] = (msg_t)v[j];
             }
@@ -204,13 +204,13 @@ __device__ __forceinline__ void hbm_decode(const DecodeArgs &a, const DevCode *c
                     if (i < d) sum += r[i];
 #pragma unroll
                 for (int i = 0; i < kMaxDv; ++i)
-                    if (i < d) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
+                    if (i < d) msg[idx[i]] = (msg_t)sat<FMT>(sum - r[i]);
                 Q = sum;
             }
             if constexpr (POST) {
                 float qv;
                 if constexpr (FMT == 0) qv = Q;
-                else qv = (float)Q * 0.0625f;
+                else qv = (float)Q * Fmt<FMT>::post_scale;
                 a.post[shot * N + C * L + 64 * h + lane] = qv;
             }
             const uint64_t m = ballot(Q < (acc_t)0);

@@ -29,8 +29,9 @@
 // gamma_n in increasing check index, alpha * min rounded once, no
 // contraction.  Priors are canonicalised with + 0.0f so no message is -0.0;
 // the raw sign bit of q is then [q < 0] and the sign product is an XOR of
-// sign bits.  int8 (Q4 priors): |q| in [0, 127], r = sign * ((num * min) >>
-// sh), integer sums exact, q saturated to [-127, 127].
+// sign bits.  Integer formats (int8 with Q4 priors, int16 with Q8 priors):
+// |q| in [0, qmax], r = sign * ((num * min) >> sh), integer sums exact, q
+// saturated to [-qmax, qmax] with qmax = 127 or 32767.
 #pragma once
 #include <stdint.h>
 
@@ -52,6 +53,7 @@ namespace qldpc {
 template <int FMT> struct Knobs;
 template <> struct Knobs<0> { static constexpr int sched_group = 0, vn_batch = 4, wave_cap = 1; };
 template <> struct Knobs<1> { static constexpr int sched_group = 1, vn_batch = 2, wave_cap = 4; };
+template <> struct Knobs<2> { static constexpr int sched_group = 1, vn_batch = 2, wave_cap = 4; };
 // Register-resident FP32 messages (see wave_decode): one block column at a
 // time keeps the scalar working set (shifts, rotated ballots) within the
 // scalar register file.
@@ -77,9 +79,27 @@ struct Geo {
     static constexpr uint64_t SEGMASK = L >= 64 ? ~0ull : ((1ull << L) - 1);
 };
 
+// Message formats: 0 = FP32; 1 = int8 messages, Q4 priors; 2 = int16
+// messages, Q8 priors (the reduced-precision integer types of Section 3,
+// Table 1).  q_t holds a layered a-posteriori value: |Q| <= qmax + d_v
+// (3 qmax >> 2), which needs 16 bits for int8 and 32 for int16.  The reported
+// posterior is Q * post_scale.
 template <int FMT> struct Fmt;
-template <> struct Fmt<0> { using msg_t = float; using q_t = float; using prior_t = float; };
-template <> struct Fmt<1> { using msg_t = int8_t; using q_t = int16_t; using prior_t = int8_t; };
+template <> struct Fmt<0> {
+    using msg_t = float; using q_t = float; using prior_t = float;
+    static constexpr int qmax = 0;
+    static constexpr float post_scale = 1.0f;
+};
+template <> struct Fmt<1> {
+    using msg_t = int8_t; using q_t = int16_t; using prior_t = int8_t;
+    static constexpr int qmax = 127;
+    static constexpr float post_scale = 0.0625f;
+};
+template <> struct Fmt<2> {
+    using msg_t = int16_t; using q_t = int32_t; using prior_t = int16_t;
+    static constexpr int qmax = 32767;
+    static constexpr float post_scale = 0.00390625f;
+};
 
 // LDS of one wave.  REG: messages live in registers; only the staging of
 // the packed decisions remains.
@@ -178,10 +198,10 @@ __device__ __forceinline__ void cn_f32(float (&v)[DC], uint32_t P, float alpha) 
     }
 }
 
-// ---- check-node rule, int8: magnitudes in [0, 127], alpha = num / 2^sh
-//      applied to the magnitude and rounded down, before the sign.
+// ---- check-node rule, integer formats: magnitudes in [0, qmax], alpha =
+//      num / 2^sh applied to the magnitude and rounded down, before the sign.
 template <int DC>
-__device__ __forceinline__ void cn_i8(int (&v)[DC], uint32_t P, int num, int sh) {
+__device__ __forceinline__ void cn_fx(int (&v)[DC], uint32_t P, int num, int sh) {
     int a[DC];
 #pragma unroll
     for (int j = 0; j < DC; ++j) a[j] = v[j] < 0 ? -v[j] : v[j];
@@ -203,7 +223,12 @@ __device__ __forceinline__ void cn_i8(int (&v)[DC], uint32_t P, int num, int sh)
     }
 }
 
-__device__ __forceinline__ int sat127(int x) { return min(127, max(-127, x)); }
+// Saturation of a message of an integer format to [-qmax, qmax].
+template <int FMT>
+__device__ __forceinline__ int sat(int x) {
+    constexpr int Q = Fmt<FMT>::qmax;
+    return min(Q, max(-Q, x));
+}
 
 // The value of lane 0, as a wave-uniform (scalar) value.
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -276,7 +301,7 @@ struct ShotRef {
 // this lane).  `lds` points to WaveLds<S, L, FMT, SCHED, NG, REG>::bytes.
 //
 // REG (L <= 64, one group): the lane's entry of every slot row is kept in a
-// register array m[slot] instead of LDS (int8 messages as 32-bit integers).  Flooding: the check pass
+// register array m[slot] instead of LDS (integer messages as 32-bit integers).  Flooding: the check pass
 // works on registers only; the variable pass fetches the entry a variable
 // reaches through a block of shift s from lane (t - s) mod L with a
 // cross-lane permute (ds_bpermute) and returns its new message to lane
@@ -298,7 +323,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     using prior_t = typename Fmt<FMT>::prior_t;
     using acc_t = typename std::conditional<FMT == 0, float, int>::type;
     static_assert(L <= 64 || NG == 1, "L = 128 uses both halves for one shot");
-    static_assert(!REG || (L <= 64 && NG == 1 && !(WEIGHTED && (SCHED == 1 || FMT == 1))),
+    static_assert(!REG || (L <= 64 && NG == 1 && !(WEIGHTED && (SCHED == 1 || FMT != 0))),
                   "register-resident messages: L <= 64, one group");
     constexpr bool GRP = L <= 64;                 // halves are independent groups
     constexpr int H = GRP ? NG : L / 64;          // halves per lane
@@ -477,7 +502,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
 #pragma unroll
                         for (int j = 0; j < DC; ++j)
                             v[j] = REG ? (int)m[R * DC + j] : (int)msg[(R * DC + j) * ROW + lane + 64 * h];
-                        cn_i8<DC>(v, P, a.alpha_num, a.alpha_shift);
+                        cn_fx<DC>(v, P, a.alpha_num, a.alpha_shift);
 #pragma unroll
                         for (int j = 0; j < DC; ++j) {
                             if constexpr (REG) m[R * DC + j] = (acc_t)v[j];
@@ -502,10 +527,10 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                         // Q of the variable (C, t + s) this lane's check sees, minus the old r
                         v[j] = bperm(cn_src(shift_of(R * DC + j)), Qv[C]) - m[R * DC + j];
                         if constexpr (FMT == 0) c[j] = v[j];
-                        else c[j] = sat127(v[j]);      // check-node input
+                        else c[j] = sat<FMT>(v[j]);      // check-node input
                     });
                     if constexpr (FMT == 0) cn_f32<DC>(c, P, a.alpha);
-                    else cn_i8<DC>(c, P, a.alpha_num, a.alpha_shift);
+                    else cn_fx<DC>(c, P, a.alpha_num, a.alpha_shift);
                     static_for<0, DC>([&](auto Jc) {
                         constexpr int j = decltype(Jc)::value;
                         constexpr int C = S::T.slot_bc[R][j];
@@ -544,9 +569,9 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
 #pragma unroll
                         for (int j = 0; j < DC; ++j) {
                             v[j] = (int)Qs[qi[j]] - rold[j];     // exact
-                            c[j] = sat127(v[j]);                 // check-node input
+                            c[j] = sat<FMT>(v[j]);                 // check-node input
                         }
-                        cn_i8<DC>(c, P, a.alpha_num, a.alpha_shift);
+                        cn_fx<DC>(c, P, a.alpha_num, a.alpha_shift);
 #pragma unroll
                         for (int j = 0; j < DC; ++j) {
                             Qs[qi[j]] = (q_t)(v[j] + c[j]);
@@ -634,11 +659,11 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                                 static_for<0, d>([&](auto Ii) {
                                     constexpr int i = decltype(Ii)::value;
                                     constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
-                                    m[slot] = (acc_t)bperm(cn_src(shift_of(slot)), sat127(sum - (int)r[i]));
+                                    m[slot] = (acc_t)bperm(cn_src(shift_of(slot)), sat<FMT>(sum - (int)r[i]));
                                 });
                             } else {
 #pragma unroll
-                                for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat127(sum - r[i]);
+                                for (int i = 0; i < d; ++i) msg[idx[i]] = (msg_t)sat<FMT>(sum - r[i]);
                             }
                             Q = sum;
                         }
@@ -743,7 +768,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                                 if (grp(h) != q) continue;
                                 float qv;
                                 if constexpr (FMT == 0) qv = Qr[C * H + h];
-                                else qv = (float)Qr[C * H + h] * 0.0625f;
+                                else qv = (float)Qr[C * H + h] * Fmt<FMT>::post_scale;
                                 a.post[shot * G::N + C * L + p + posoff(h)] = qv;
                             }
                     }
@@ -852,6 +877,19 @@ hipError_t launch_wreg(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) 
     else if (k.fmt == 0 && k.sched == 1) launch_wreg_sched<S, L, 1, 0>(k, a, grid, st);
     else if (k.fmt == 1 && k.sched == 0) launch_wreg_sched<S, L, 0, 1>(k, a, grid, st);
     else if (k.fmt == 1 && k.sched == 1) launch_wreg_sched<S, L, 1, 1>(k, a, grid, st);
+    else return hipErrorNotSupported;
+    return hipGetLastError();
+}
+
+// int16 messages (FMT = 2), both schedules; instantiated in files of their
+// own so that they compile in parallel with the FP32 and int8 kernels.
+template <class S, int L>
+hipError_t launch_wreg_i16(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
+    using G = Geo<S, L>;
+    const unsigned grid = (unsigned)((a.batch + G::SPW - 1) / G::SPW);
+    if (k.fmt != 2) return hipErrorNotSupported;
+    if (k.sched == 0) launch_wreg_sched<S, L, 0, 2>(k, a, grid, st);
+    else if (k.sched == 1) launch_wreg_sched<S, L, 1, 2>(k, a, grid, st);
     else return hipErrorNotSupported;
     return hipGetLastError();
 }

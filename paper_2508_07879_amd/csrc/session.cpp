@@ -275,7 +275,7 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
     s->io_mode = io_mode;
     s->syn_words = (code->m + 31) / 32;
     s->err_words = (code->n + 31) / 32;
-    const size_t vbytes = params->fmt == QLDPC_F32 ? 4 : 1;
+    const size_t vbytes = params->fmt == QLDPC_F32 ? 4 : params->fmt == QLDPC_I16Q8 ? 2 : 1;
     s->prior_bytes_per_shot = params->prior_mode == QLDPC_PRIOR_PER_BIT ? vbytes * code->n : vbytes;
     const size_t B = (size_t)max_batch;
     // MAPPED: fine-grained (coherent) pinned memory the kernel reads and writes

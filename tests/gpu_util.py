@@ -21,10 +21,7 @@ def gpu_decode(dec, s_bits, prior, fmt=0, sched=0, alpha=0.75, max_iters=32, ear
     """Decode uint8 syndrome bits [B, m] on the device; returns host arrays."""
     import torch
     syn = to_dev(bits.pack_bits(s_bits).view(np.int32))
-    if fmt == 0:
-        pr = to_dev(np.asarray(prior, np.float32))
-    else:
-        pr = to_dev(np.asarray(prior, np.int8))
+    pr = to_dev(np.asarray(prior, {0: np.float32, 1: np.int8, 2: np.int16}[fmt]))
     p = dec.params(fmt=fmt, sched=sched, alpha=alpha, max_iters=max_iters, early_stop=early_stop,
                    per_bit=per_bit, layout=layout, waves_per_shot=waves_per_shot)
     err, conv, it, post = dec.decode(syn, pr, p, posterior=posterior)
@@ -40,6 +37,11 @@ def oracle_decode(H, s_bits, prior, fmt=0, sched=0, alpha=0.75, max_iters=32, ea
         return oracle.flood_f32(H, s_bits, prior, alpha=alpha, max_iters=max_iters, early_stop=early_stop)
     if fmt == 1 and sched == 0:
         return oracle.flood_i8(H, s_bits, prior, alpha=alpha, max_iters=max_iters, early_stop=early_stop)
+    if fmt == 2 and sched == 0:
+        return oracle.flood_i16(H, s_bits, prior, alpha=alpha, max_iters=max_iters, early_stop=early_stop)
+    if fmt == 2:
+        return oracle.layered_i16(H, s_bits, prior, layer_size, alpha=alpha, max_iters=max_iters,
+                                  early_stop=early_stop)
     if fmt == 0 and sched == 1:
         return oracle.layered_f32(H, s_bits, prior, layer_size, alpha=alpha, max_iters=max_iters,
                                   early_stop=early_stop)
@@ -49,14 +51,15 @@ def oracle_decode(H, s_bits, prior, fmt=0, sched=0, alpha=0.75, max_iters=32, ea
 
 def assert_parity(g, o, prior_scale, fmt, tag=""):
     """Identical e / converged / iterations; posterior within 1e-5 relative
-    (FP32: |dQ| <= 1e-5 * max(|Q_oracle|, |gamma|)), bit-exact for int8."""
+    (FP32: |dQ| <= 1e-5 * max(|Q_oracle|, |gamma|)), bit-exact for int8 and
+    int16."""
     e, conv, it, post = g
     bad = np.nonzero(~np.all(e == o.e, axis=1) | (conv != o.converged) | (it != o.iters))[0]
     assert bad.size == 0, (f"{tag}: {bad.size} shots differ, first {bad[:8].tolist()}; "
                            f"gpu iters {it[bad[:4]].tolist()} oracle {o.iters[bad[:4]].tolist()}")
     if post is not None:
-        if fmt == 1:
-            assert np.array_equal(post, o.Q), f"{tag}: int8 posterior not bit-exact"
+        if fmt != 0:
+            assert np.array_equal(post, o.Q), f"{tag}: integer posterior not bit-exact"
         else:
             tol = 1e-5 * np.maximum(np.abs(o.Q), np.abs(prior_scale))
             d = np.abs(post - o.Q)
