@@ -127,20 +127,24 @@ typedef enum {
 } qldpc_prior_mode;
 
 typedef enum {
-    QLDPC_LAYOUT_AUTO = 0,   /* tuned choice for (code, format, batch)       */
+    QLDPC_LAYOUT_AUTO = 0,   /* tuned choice for (code, format, batch) when
+                                qldpc_autotune recorded one; otherwise:
+                                L >= 256 HBM; flooding at L = 128, or at
+                                L = 64 with batch < 512, BLOCK (16 waves
+                                below 512 shots, else 8); otherwise
+                                WAVE_REG for L <= 64, WAVE for L = 128     */
     QLDPC_LAYOUT_WAVE = 1,   /* one wavefront decodes one shot (or 64 / L
                                 shots when L < 64); throughput layout        */
     QLDPC_LAYOUT_BLOCK = 2,  /* one workgroup of several wavefronts decodes
-                                one shot; latency layout                     */
+                                one shot, messages in LDS; flooding, L >= 64;
+                                the latency layout, and AUTO's throughput
+                                layout at L = 128 (8 wavefronts)            */
     QLDPC_LAYOUT_HBM = 4,    /* one workgroup decodes one shot with its edge
                                 messages in a caller-provided device
                                 workspace (qldpc_decode_batch_ws): codes too
                                 large for on-chip messages; flooding with
                                 L in {128, 256, 512}; AUTO picks it for
-                                L >= 256, and, when a workspace can be given
-                                (qldpc_decode_workspace_bytes,
-                                qldpc_decode_batch_ws), for FP32 at L = 128
-                                with batch >= 512, where it is faster       */
+                                L >= 256                                    */
     QLDPC_LAYOUT_WAVE_REG = 3 /* as WAVE, with every message (and, layered,
                                 every a-posteriori value) kept in the lanes'
                                 registers and moved between lanes by
@@ -295,10 +299,9 @@ typedef struct qldpc_mixed_s *qldpc_mixed;
 /* Plan over 1..8 code objects on one device for batches of up to
  * max_batch shots (FP32 flooding, per-shot priors; params gives alpha,
  * iterations and early stop; lifts 16, 32, 64 and 128).  Allocates
- * 4 * (max_batch + 24) bytes of device scratch, plus 61440 bytes per L = 128
- * workgroup (four per compute unit) when a code has L = 128.  One persistent
- * grid per (pattern, lift size) decodes its shots: messages in registers for
- * L <= 64, in that HBM workspace for L = 128.  use_graph = 1: every distinct argument set is captured
+ * 4 * (max_batch + 24) bytes of device scratch.  One persistent grid per
+ * (pattern, lift size) decodes its shots: messages in registers for L <= 64,
+ * in the LDS of 8-wave workgroups (two per compute unit) for L = 128.  use_graph = 1: every distinct argument set is captured
  * once as a hipGraph (bucketing kernels + persistent decoders) and
  * replayed. */
 qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const qldpc_decode_params *params,

@@ -44,7 +44,7 @@ qldpc_status hip_fail(hipError_t e, const char *what) { return hip_error(e, what
 namespace qldpc {
 
 qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32_t batch, LaunchKey *key,
-                            DecodeArgs *a, bool ws_ok) {
+                            DecodeArgs *a) {
     if (!code || !p) return fail(QLDPC_ERR_INVALID_ARG, "decode: null code or params");
     if (batch < 0) return fail(QLDPC_ERR_INVALID_ARG, "decode: negative batch");
     if (p->max_iters < 1 || p->max_iters > 255)
@@ -85,12 +85,6 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     const bool block_ok = p->sched == QLDPC_FLOOD && code->L >= 64;
     int layout = p->layout, nw = p->waves_per_shot;
     if (layout == QLDPC_LAYOUT_AUTO && code->L > 128) layout = QLDPC_LAYOUT_HBM;   // messages do not fit on chip
-    // FP32 flooding at L = 128 holds 77 KB of LDS per shot (two waves per compute
-    // unit); with a workspace, messages in device memory are faster there
-    // (3.5 vs 2.4 M syndromes/s on MI355X, 32768 shots, p = 0.03).
-    if (layout == QLDPC_LAYOUT_AUTO && ws_ok && code->L == 128 && p->fmt == QLDPC_F32 && p->sched == QLDPC_FLOOD &&
-        batch >= 512)
-        layout = QLDPC_LAYOUT_HBM;
     if (layout == QLDPC_LAYOUT_AUTO) {
         bool found = false;
         {
@@ -102,11 +96,22 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
                 found = true;
             }
         }
+        // Defaults measured on MI355X (65536 shots at L = 64, 32768 at L = 128,
+        // p = 0.01 / 0.03 / 0.05): at L <= 64 messages in registers (FP32
+        // flooding 32.0 M syndromes/s against 26.9 M for 8-wave workgroups); at
+        // L = 128 flooding an 8-wave workgroup per shot with messages in LDS
+        // (7.8 M FP32, 7.75 M int8, against 3.3 / 4.55 M with messages in HBM
+        // and 2.3 / 7.0 M for a wavefront per shot); small batches (latency)
+        // 16-wave workgroups.
         const bool reg_ok = code->L <= 64;
-        if (!found)
-            layout = (block_ok && batch < 512) ? QLDPC_LAYOUT_BLOCK
-                     : reg_ok                  ? QLDPC_LAYOUT_WAVE_REG
-                                               : QLDPC_LAYOUT_WAVE;
+        if (!found) {
+            if (block_ok && (batch < 512 || code->L == 128)) {
+                layout = QLDPC_LAYOUT_BLOCK;
+                if (nw == 0) nw = batch < 512 ? 16 : 8;
+            } else {
+                layout = reg_ok ? QLDPC_LAYOUT_WAVE_REG : QLDPC_LAYOUT_WAVE;
+            }
+        }
     }
     if (layout == QLDPC_LAYOUT_BLOCK) {
         if (!block_ok)
@@ -313,7 +318,7 @@ qldpc_status decode_impl(qldpc_code code, const qldpc_decode_params *p, int32_t 
                          void *ws, size_t ws_bytes, void *stream, const char *who) {
     LaunchKey k{};
     DecodeArgs a{};
-    qldpc_status st = prepare_decode(code, p, batch, &k, &a, with_ws);
+    qldpc_status st = prepare_decode(code, p, batch, &k, &a);
     if (st != QLDPC_OK || batch == 0) return st;
     if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, std::string(who) + ": null buffer");
     const size_t need = workspace_bytes_for(code, k, batch);
@@ -353,7 +358,7 @@ qldpc_status qldpc_decode_workspace_bytes(qldpc_code code, const qldpc_decode_pa
     if (!bytes) return fail(QLDPC_ERR_INVALID_ARG, "decode_workspace_bytes: null output");
     LaunchKey k{};
     DecodeArgs a{};
-    qldpc_status st = prepare_decode(code, p, batch, &k, &a, true);
+    qldpc_status st = prepare_decode(code, p, batch, &k, &a);
     if (st != QLDPC_OK) return st;
     *bytes = workspace_bytes_for(code, k, batch);
     return QLDPC_OK;

@@ -77,10 +77,15 @@ struct BlockLds {
     static constexpr size_t bytes = s_off + (((size_t)S::MB * L + 31) / 32) * 4;
 };
 
-// Decodes shot `shot` with the whole workgroup; `lds` holds
-// BlockLds<S, L, FMT, NW>::bytes.  Every thread of the workgroup must call it.
+// Decodes shot `shot` of the code whose shift table is `code_table` (its
+// syndrome words at syn, error words to err; priors, flags and posteriors
+// indexed by shot) with the whole workgroup.  a.code, a.syn and a.err are not
+// used: the mixed-code path passes each shot's own table and ragged offsets.
+// `lds` holds BlockLds<S, L, FMT, NW>::bytes.  Every thread of the workgroup
+// must call it.
 template <class S, int L, int FMT, int NW, bool PER_BIT, bool POST>
-__device__ __forceinline__ void block_decode(const DecodeArgs &a, const long shot, unsigned char *lds) {
+__device__ __forceinline__ void block_decode(const DecodeArgs &a, const DevCode *code_table, const long shot,
+                                             const uint32_t *syn, uint32_t *err, unsigned char *lds) {
     using namespace wave;
     static_assert(L == 64 || L == 128, "block layout needs L >= 64");
     using Lay = BlockLds<S, L, FMT, NW>;
@@ -100,12 +105,12 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const long sho
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const CodePtr code = const_code(a.code);
+    const CodePtr code = const_code(code_table);
     uint32_t *synw = reinterpret_cast<uint32_t *>(lds + Lay::s_off);
 
     // the shot's syndrome words are read from memory once per workgroup (the
     // latency path reads them across the bus) and shared through LDS
-    for (int w = threadIdx.x; w < SW; w += 64 * NW) synw[w] = a.syn[shot * SW + w];
+    for (int w = threadIdx.x; w < SW; w += 64 * NW) synw[w] = syn[w];
     // priors of this wave's variable items (canonicalised: no message is -0.0)
     acc_t gam[PER_BIT ? VN_PER_WAVE : 1];
     if constexpr (!PER_BIT) {
@@ -161,7 +166,7 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const long sho
         // e words straight from the ballots; conv / iters by thread 0
         for (int w = threadIdx.x; w < EW; w += 64 * NW) {
             const uint64_t m = emask[(w * 32) / 64];
-            a.err[shot * EW + w] = (uint32_t)(m >> ((w * 32) % 64));
+            err[w] = (uint32_t)(m >> ((w * 32) % 64));
         }
         if (threadIdx.x == 0) {
             a.conv[shot] = conv ? 1 : 0;
@@ -305,7 +310,8 @@ __global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[BlockLds<S, L, FMT, NW>::bytes];
     const long shot = blockIdx.x;
     if (a.only && a.only[shot] == 0) return;   // uniform over the workgroup
-    block_decode<S, L, FMT, NW, PER_BIT, POST>(a, shot, lds);
+    constexpr int SW = (S::MB * L + 31) / 32, EW = (S::NB * L + 31) / 32;
+    block_decode<S, L, FMT, NW, PER_BIT, POST>(a, a.code, shot, a.syn + shot * SW, a.err + shot * EW, lds);
 }
 
 template <class S, int L, int FMT, int NW, bool PB, bool PO>

@@ -8,19 +8,19 @@
 // wavefronts per (block pattern, lift size) then claims tiles of same-code
 // shots from its own atomic counter until none are left: for L <= 64 every
 // message stays in registers (one 64-lane group of 64 / L shots per tile),
-// for L = 128 in a plan-owned HBM workspace, one slot per persistent
-// workgroup of 8 waves (one shot per tile).  Codes of both patterns (H_Z and
+// for L = 128 in the LDS of a persistent workgroup of 8 waves running the
+// workgroup-per-shot decoder (one shot per tile).  Codes of both patterns (H_Z and
 // H_X of one CSS code, say) can share a batch, so both sides of a code are
 // decoded in one launch sequence.  Each shot's result depends only on its
 // own syndrome and prior, never on its tile mates or grid.
 #pragma once
-#include "decode_hbm.h"
+#include "decode_block.h"
 #include "decode_wave.h"
 
 namespace qldpc {
 
 constexpr int kMaxMixCodes = 8;
-constexpr int kMixHbmWaves = 8;   // waves per workgroup of the L = 128 grid
+constexpr int kMixBlockWaves = 8;   // waves per workgroup of the L = 128 grid
 
 struct MixedArgs {
     DecodeArgs base;                       // alpha, iterations, priors, conv / iters outputs
@@ -35,7 +35,6 @@ struct MixedArgs {
     const uint32_t *syn;
     uint32_t *err;
     int32_t *scratch;                      // counts[8], cursors[8], tile counters[8], order[batch]
-    float *hbm_ws;                         // L = 128 messages: [grid][120 * 128]
     int32_t batch;
 };
 
@@ -162,16 +161,16 @@ __device__ __forceinline__ void mix_locate(const MixedArgs &m, int t, int &c, in
     }
 }
 
-// Persistent decoder of the L = 128 shots with messages in HBM: each
-// workgroup claims one shot at a time and decodes it in its own workspace
-// slot.  Every value that decides whether a wave reaches a barrier is
-// workgroup-uniform (broadcast through LDS, then readfirstlane).
+// Persistent decoder of the L = 128 shots: each 8-wave workgroup claims one
+// shot at a time and decodes it with its messages in LDS (61 KB FP32, two
+// workgroups per compute unit).  Every value that decides whether a wave
+// reaches a barrier is workgroup-uniform (broadcast through LDS, then
+// readfirstlane).
 template <class S>
-__global__ __launch_bounds__(64 * kMixHbmWaves) void k_mix_hbm(const MixedArgs m) {
-    constexpr int L = 128, NW = kMixHbmWaves;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[HbmLds<S, L, NW>::bytes];
+__global__ __launch_bounds__(64 * kMixBlockWaves) void k_mix_block(const MixedArgs m) {
+    constexpr int L = 128, NW = kMixBlockWaves;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[BlockLds<S, L, 0, NW>::bytes];
     __shared__ int tile;
-    float *msg = m.hbm_ws + (long)blockIdx.x * (S::SLOTS * L);
     for (;;) {
         if (threadIdx.x == 0) tile = atomicAdd(mix::tile_ctr(m, S::WHICH, L), 1);
         __syncthreads();
@@ -183,7 +182,7 @@ __global__ __launch_bounds__(64 * kMixHbmWaves) void k_mix_hbm(const MixedArgs m
         const long shot = (long)(int64_t)wave::uniform64((uint64_t)(int64_t)mix::order(m)[first]);
         const int64_t so = (int64_t)wave::uniform64((uint64_t)m.syn_off[shot]);
         const int64_t eo = (int64_t)wave::uniform64((uint64_t)m.err_off[shot]);
-        hbm_decode<S, L, 0, NW, false, false>(m.base, m.codes[c], shot, m.syn + so, m.err + eo, msg, lds);
+        block_decode<S, L, 0, NW, false, false>(m.base, m.codes[c], shot, m.syn + so, m.err + eo, lds);
         __syncthreads();   // LDS reused by the next shot
     }
 }

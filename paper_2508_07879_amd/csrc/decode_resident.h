@@ -37,6 +37,7 @@ template <class S, int L, int FMT, int NW, bool PER_BIT>
 __global__ __launch_bounds__(64 * NW) void k_resident(const ResidentArgs r) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[BlockLds<S, L, FMT, NW>::bytes];
     __shared__ uint64_t req[2];   // [sequence or kResidentExit, batch]
+    constexpr int kSW = (S::MB * L + 31) / 32, kEW = (S::NB * L + 31) / 32;
     const int wg = blockIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(64 * NW) void k_resident(const ResidentArgs r) {
             // Wave 0 acquired at system scope after it saw the request; the
             // barriers above order the other waves of the workgroup (one
             // compute unit, one L1) after that acquire.
-            block_decode<S, L, FMT, NW, PER_BIT, false>(r.a, wg, lds);
+            block_decode<S, L, FMT, NW, PER_BIT, false>(r.a, r.a.code, wg, r.a.syn + wg * kSW, r.a.err + wg * kEW,
+                                                        lds);
             // Each wave waits until its own result stores have completed, then
             // thread 0 answers with a system-scope release store (one L2
             // write-back per request instead of one per wave).

@@ -49,9 +49,7 @@ namespace qldpc {
 
 // Validates `p` against `code` and fills the launch key and kernel
 // arguments for a decode of `batch` shots (buffers set by the caller).
-// ws_ok: the caller can supply a message workspace, so AUTO may choose
-// device-memory messages where they are faster.
 qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32_t batch, LaunchKey *key,
-                            DecodeArgs *args, bool ws_ok = false);
+                            DecodeArgs *args);
 
 }  // namespace qldpc

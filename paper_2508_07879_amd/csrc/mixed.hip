@@ -17,8 +17,7 @@ struct qldpc_mixed_s {
     qldpc_code codes[kMaxMixCodes] = {};
     qldpc_decode_params params{};
     int32_t waves = 0;              // persistent grid size for each lift L <= 64 (registers)
-    int32_t waves128 = 0;           // workgroups of the L = 128 grid (messages in HBM)
-    float *hbm_ws = nullptr;        // device: one message slot per L = 128 workgroup
+    int32_t waves128 = 0;           // workgroups of the L = 128 grid (messages in LDS)
     bool has_grid[mix::kMixGrids] = {};   // (pattern, L) pairs among the plan's codes
     int32_t *scratch = nullptr;     // device
     std::mutex mu;
@@ -60,7 +59,6 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
     m.syn = syn;
     m.err = err;
     m.scratch = x->scratch;
-    m.hbm_ws = x->hbm_ws;
     m.batch = batch;
     const unsigned nb = (unsigned)((batch + 255) / 256);
     hipLaunchKernelGGL(k_mix_clear, dim3(1), dim3(64), 0, st, m);
@@ -69,9 +67,9 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
     // one persistent grid per (pattern, lift size) present, largest L first
     const unsigned w64 = (unsigned)waves, w128 = (unsigned)x->waves128;
     const bool *g = x->has_grid;
-    const dim3 hb(64 * kMixHbmWaves);
-    if (g[3]) hipLaunchKernelGGL((k_mix_hbm<ShapeLP35Z>), dim3(w128), hb, 0, st, m);
-    if (g[7]) hipLaunchKernelGGL((k_mix_hbm<ShapeLP35X>), dim3(w128), hb, 0, st, m);
+    const dim3 hb(64 * kMixBlockWaves);
+    if (g[3]) hipLaunchKernelGGL((k_mix_block<ShapeLP35Z>), dim3(w128), hb, 0, st, m);
+    if (g[7]) hipLaunchKernelGGL((k_mix_block<ShapeLP35X>), dim3(w128), hb, 0, st, m);
     if (g[2]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 64>), dim3(w64), dim3(64), 0, st, m);
     if (g[6]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 64>), dim3(w64), dim3(64), 0, st, m);
     if (g[1]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 32>), dim3(w64), dim3(64), 0, st, m);
@@ -111,7 +109,7 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
     x->waves = 12 * cus;     // register grids: up to three waves per SIMD
-    x->waves128 = 4 * cus;   // L = 128: four 8-wave workgroups per CU, messages in HBM
+    x->waves128 = 2 * cus;   // L = 128: two 8-wave workgroups per CU (61 KB of LDS each)
     for (int c = 0; c < ncodes; ++c) {
         const int L = codes[c]->L;
         if (L != 16 && L != 32 && L != 64 && L != 128) {
@@ -122,8 +120,6 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
     }
     hipError_t e = hipSetDevice(x->device);
     if (e == hipSuccess) e = hipMalloc(&x->scratch, sizeof(int32_t) * (mix::kScratchHead + (size_t)max_batch));
-    if (e == hipSuccess && (x->has_grid[3] || x->has_grid[7]))
-        e = hipMalloc(&x->hbm_ws, sizeof(float) * (size_t)x->waves128 * 120 * 128);
     if (e != hipSuccess) {
         if (x->scratch) (void)hipFree(x->scratch);
         delete x;
@@ -137,7 +133,6 @@ qldpc_status qldpc_mixed_destroy(qldpc_mixed x) {
     if (!x) return QLDPC_OK;
     for (auto &kv : x->graphs) (void)hipGraphExecDestroy(kv.second);
     if (x->scratch) (void)hipFree(x->scratch);
-    if (x->hbm_ws) (void)hipFree(x->hbm_ws);
     delete x;
     return QLDPC_OK;
 }

@@ -91,11 +91,13 @@ def test_workspace_contract_and_rejections():
     assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(fmt=abi.QLDPC_I8Q4), B) == B * 120 * 256
     c64, sd64, _, dec64 = side(64)
     assert abi.qldpc_decode_workspace_bytes(dec64.handle, dec64.params(), B) == 0
-    # L = 128: AUTO with a workspace takes device-memory messages for FP32 batches >= 512
+    # L = 128: AUTO keeps messages on chip (8-wave workgroups, LDS); asked for
+    # explicitly, the HBM layout needs its workspace
     c128, sd128, _, dec128 = side(128)
-    assert abi.qldpc_decode_workspace_bytes(dec128.handle, dec128.params(), 1024) == 1024 * 120 * 128 * 4
+    assert abi.qldpc_decode_workspace_bytes(dec128.handle, dec128.params(), 1024) == 0
     assert abi.qldpc_decode_workspace_bytes(dec128.handle, dec128.params(), 100) == 0
     assert abi.qldpc_decode_workspace_bytes(dec128.handle, dec128.params(fmt=abi.QLDPC_I8Q4), 1024) == 0
+    assert abi.qldpc_decode_workspace_bytes(dec128.handle, dec128.params(layout=HBM), 1024) == 1024 * 120 * 128 * 4
     syn = torch.zeros((B, dec.syn_words), dtype=torch.int32, device="cuda")
     pr = torch.full((B,), 3.0, device="cuda")
     err, conv, it, _ = dec.outputs(B)
