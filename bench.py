@@ -340,13 +340,40 @@ def main():
                 latency[mode_name] = per_p
             finally:
                 abi.qldpc_session_destroy(sess)
+        # both sides of the CSS code per request: the H_Z syndrome of X errors
+        # and the H_X syndrome of independent Z errors at the same rate
+        dec_x = Decoder(code.hx, device=0)
+        both = {}
+        for early in (False, True):
+            prm = dec.params(max_iters=32, early_stop=early, layout=abi.QLDPC_LAYOUT_BLOCK)
+            sess = abi.qldpc_session_create_css(dec.handle, dec_x.handle, prm, 1)
+            try:
+                for bb in batches:
+                    bx = noise.Batch(code.hx, args.seed + 50 + int(bb["p"] * 1000), np.arange(pool), bb["p"])
+                    syn_h = np.ascontiguousarray(np.stack([bits.pack_bits(bb["batch"].s[:pool]),
+                                                           bits.pack_bits(bx.s)], axis=1).reshape(2 * pool, -1))
+                    pr_h = np.ascontiguousarray(np.stack([bb["batch"].gamma[:pool], bx.gamma], axis=1).reshape(-1))
+                    nreq = max(1, args.latency_reqs // 5)
+                    abi.qldpc_session_latency(sess, 500, 1, pool, syn_h, pr_h)      # warm-up
+                    lat = abi.qldpc_session_latency(sess, nreq, 1, pool, syn_h, pr_h)
+                    st = lat_stats(lat)
+                    key = ("early_stop_p" if early else "all_32_iterations_p") + str(bb["p"])
+                    both[key] = st
+                    print(json.dumps({"latency": "both_css_sides", "case": key, **st}), file=sys.stderr, flush=True)
+                    if not early:
+                        break
+            finally:
+                abi.qldpc_session_destroy(sess)
+        latency["both_css_sides"] = both
         latency["definition"] = ("one syndrome per request, from host memory to the decision in host memory, "
                                  "steady-clock per request; FP32 flooding, workgroup-per-shot layout (16 waves). "
                                  "early_stop and all_32_iterations: resident decoder woken through a doorbell in "
                                  "fine-grained host memory (no launch, no stream synchronisation per request); "
                                  "all_32_iterations_launch_per_request: one kernel launch and stream "
                                  "synchronisation per request, same buffers; batch_64_early_stop: 64 syndromes "
-                                 "per request (p = 0.01), one workgroup per syndrome")
+                                 "per request (p = 0.01), one workgroup per syndrome; both_css_sides: one "
+                                 "request = the H_Z syndrome of X errors and the H_X syndrome of independent Z "
+                                 "errors at the same rate, decoded together by one resident grid")
 
     # ---------------- CPU oracle on a bounded sample ---------------------------
     cpu = None

@@ -270,9 +270,26 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
                                   int32_t max_batch, int32_t io_mode, qldpc_session *out);
 qldpc_status qldpc_session_destroy(qldpc_session s);
 
+/* A resident session over the two sides of one CSS code (the paper decodes
+ * the X and Z syndromes of a round together, Section 2): hz_side has the
+ * H_Z block pattern and hx_side the H_X pattern of the same lift (64 or 128),
+ * on the same device.  A request item is a syndrome pair: the H_Z syndrome
+ * (of X errors) followed by the H_X syndrome (of Z errors); both are decoded
+ * at once by workgroups of the same resident grid.  With such a session,
+ * qldpc_session_decode and qldpc_session_latency count `batch` in pairs, and
+ * every per-shot buffer holds two entries per pair, H_Z side first:
+ * syndromes [batch][2][ceil(m/32)], priors [batch][2] (or [batch][2][n]),
+ * errors [batch][2][ceil(n/32)], converged and iters_used [batch][2].
+ * max_pairs in [1, 32]; FP32 or int8 (else UNSUPPORTED); io mode RESIDENT
+ * with its rules.  Errors: INVALID_ARG (null, bad sizes, patterns or lifts
+ * that do not pair), UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
+qldpc_status qldpc_session_create_css(qldpc_code hz_side, qldpc_code hx_side, const qldpc_decode_params *params,
+                                      int32_t max_pairs, qldpc_session *out);
+
 /* Synchronous decode of `batch` <= max_batch shots from host buffers
  * (syndromes uint32 [batch][ceil(m/32)], priors as in qldpc_decode_batch)
- * into host buffers (errors, converged, iters_used may be NULL). */
+ * into host buffers (errors, converged, iters_used may be NULL); for a CSS
+ * pair session, `batch` <= max_pairs pairs as described above. */
 qldpc_status qldpc_session_decode(qldpc_session s, int32_t batch, const uint32_t *host_syndromes,
                                   const void *host_priors, uint32_t *host_errors,
                                   uint8_t *host_converged, uint8_t *host_iters);

@@ -107,6 +107,7 @@ def _load():
         "qldpc_tune_save": ([vp, C.c_char_p], i32),
         "qldpc_tune_load": ([vp, C.c_char_p], i32),
         "qldpc_session_create": ([vp, C.POINTER(qldpc_decode_params), i32, i32, C.POINTER(vp)], i32),
+        "qldpc_session_create_css": ([vp, vp, C.POINTER(qldpc_decode_params), i32, C.POINTER(vp)], i32),
         "qldpc_session_destroy": ([vp], i32),
         "qldpc_session_decode": ([vp, i32, vp, vp, vp, vp, vp], i32),
         "qldpc_session_latency": ([vp, i32, i32, i32, vp, vp, vp], i32),
@@ -257,6 +258,12 @@ def _np(a):
 def qldpc_session_create(h, params: qldpc_decode_params, max_batch: int, io_mode: int = QLDPC_IO_COPY):
     s = C.c_void_p()
     _check(lib.qldpc_session_create(h, C.byref(params), int(max_batch), int(io_mode), C.byref(s)))
+    return s
+
+
+def qldpc_session_create_css(hz_handle, hx_handle, params: qldpc_decode_params, max_pairs: int):
+    s = C.c_void_p()
+    _check(lib.qldpc_session_create_css(hz_handle, hx_handle, C.byref(params), int(max_pairs), C.byref(s)))
     return s
 
 

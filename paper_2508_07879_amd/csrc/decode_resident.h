@@ -9,6 +9,11 @@
 // written by the host before it rang), makes its results visible to the
 // host, then publishes the sequence number in done_seq[w].
 //
+// CSS pairs (SX not void): the two sides of one CSS code share the grid;
+// even shots are syndromes of the H_Z pattern (table a.code), odd shots of the
+// H_X pattern (table code_x), so one request decodes both sides of each of
+// its syndrome pairs at once (the paper's unit of latency, Section 2).
+//
 // Exit: workgroup 0 leaves when the host sets `stop` or when no request has
 // arrived for `idle_ticks` of the GPU's constant wall clock, and tells the
 // others through the mailbox; they also leave on their own after twice that
@@ -33,7 +38,7 @@ using wave::uniform64;
 // compiler must treat as divergent (say, "thread 0 polls" followed by a
 // barrier in the same loop) it may let the other lanes of the wave run on to
 // the next barrier without the polling lane, which then never runs again.
-template <class S, int L, int FMT, int NW, bool PER_BIT>
+template <class S, int L, int FMT, int NW, bool PER_BIT, class SX = void>
 __global__ __launch_bounds__(64 * NW) void k_resident(const ResidentArgs r) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[BlockLds<S, L, FMT, NW>::bytes];
     __shared__ uint64_t req[2];   // [sequence or kResidentExit, batch]
@@ -97,8 +102,16 @@ __global__ __launch_bounds__(64 * NW) void k_resident(const ResidentArgs r) {
             // Wave 0 acquired at system scope after it saw the request; the
             // barriers above order the other waves of the workgroup (one
             // compute unit, one L1) after that acquire.
-            block_decode<S, L, FMT, NW, PER_BIT, false>(r.a, r.a.code, wg, r.a.syn + wg * kSW, r.a.err + wg * kEW,
-                                                        lds);
+            if constexpr (std::is_void<SX>::value) {
+                block_decode<S, L, FMT, NW, PER_BIT, false>(r.a, r.a.code, wg, r.a.syn + wg * kSW,
+                                                            r.a.err + wg * kEW, lds);
+            } else if (wg & 1) {   // uniform over the workgroup
+                block_decode<SX, L, FMT, NW, PER_BIT, false>(r.a, r.code_x, wg, r.a.syn + wg * kSW,
+                                                             r.a.err + wg * kEW, lds);
+            } else {
+                block_decode<S, L, FMT, NW, PER_BIT, false>(r.a, r.a.code, wg, r.a.syn + wg * kSW,
+                                                            r.a.err + wg * kEW, lds);
+            }
             // Each wave waits until its own result stores have completed, then
             // thread 0 answers with a system-scope release store (one L2
             // write-back per request instead of one per wave).
@@ -119,14 +132,19 @@ static __global__ void k_resident_arm(uint64_t *cmd, uint64_t seq) {
     }
 }
 
-template <class S, int L, int FMT, int NW>
+template <class S, int L, int FMT, int NW, class SX = void>
 hipError_t launch_resident(const LaunchKey &k, const ResidentArgs &r, int grid, hipStream_t st) {
     if (k.post) return hipErrorNotSupported;
+    if constexpr (!std::is_void<SX>::value) {
+        static_assert(BlockLds<SX, L, FMT, NW>::bytes == BlockLds<S, L, FMT, NW>::bytes,
+                      "the two sides of a pair share one LDS layout");
+        if (r.code_x == nullptr || grid % 2 != 0) return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL(k_resident_arm, dim3(1), dim3(64), 0, st, r.cmd, r.start_seq);
     if (k.per_bit)
-        hipLaunchKernelGGL((k_resident<S, L, FMT, NW, true>), dim3((unsigned)grid), dim3(64 * NW), 0, st, r);
+        hipLaunchKernelGGL((k_resident<S, L, FMT, NW, true, SX>), dim3((unsigned)grid), dim3(64 * NW), 0, st, r);
     else
-        hipLaunchKernelGGL((k_resident<S, L, FMT, NW, false>), dim3((unsigned)grid), dim3(64 * NW), 0, st, r);
+        hipLaunchKernelGGL((k_resident<S, L, FMT, NW, false, SX>), dim3((unsigned)grid), dim3(64 * NW), 0, st, r);
     return hipGetLastError();
 }
 

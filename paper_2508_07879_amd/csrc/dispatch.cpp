@@ -30,6 +30,8 @@ hipError_t launch_wreg_i16_L32(const LaunchKey &, const DecodeArgs &, hipStream_
 hipError_t launch_wreg_i16_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_resident_i16_L64(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
 hipError_t launch_resident_i16_L128(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
+hipError_t launch_resident_css_L64(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
+hipError_t launch_resident_css_L128(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
 hipError_t launch_resident_L64(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
 hipError_t launch_resident_L128(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
 hipError_t launch_residentx_L64(const LaunchKey &, const ResidentArgs &, int, hipStream_t);
@@ -92,6 +94,11 @@ hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t st
 
 hipError_t launch_resident_decode(const LaunchKey &k, const ResidentArgs &r, int grid, hipStream_t stream) {
     if (k.layout != 2) return hipErrorNotSupported;
+    if (k.which == 2) {   // CSS pair: FP32 and int8
+        if (k.L == 64) return launch_resident_css_L64(k, r, grid, stream);
+        if (k.L == 128) return launch_resident_css_L128(k, r, grid, stream);
+        return hipErrorNotSupported;
+    }
     if (k.fmt == 2) {
         if (k.L == 64) return launch_resident_i16_L64(k, r, grid, stream);
         if (k.L == 128) return launch_resident_i16_L128(k, r, grid, stream);

@@ -62,6 +62,7 @@ struct ResidentRing {
 // [seq, batch] through which workgroup 0 relays requests to the others.
 struct ResidentArgs {
     DecodeArgs a;
+    const DevCode *code_x;  // CSS pair sessions: the H_X side's table (odd shots); else null
     ResidentRing *ring;
     uint64_t *cmd;
     uint64_t start_seq;    // last sequence number already served
@@ -69,9 +70,9 @@ struct ResidentArgs {
 };
 
 struct LaunchKey {
-    int which;      // 0 = H_Z pattern, 1 = H_X pattern
+    int which;      // 0 = H_Z pattern, 1 = H_X pattern; 2 = a CSS pair (resident sessions)
     int L;          // 16, 32, 64, 128
-    int fmt;        // 0 = F32, 1 = I8Q4
+    int fmt;        // 0 = F32, 1 = I8Q4, 2 = I16Q8
     int sched;      // 0 = flood, 1 = layered
     int per_bit;    // prior mode
     int post;       // posterior requested

@@ -26,7 +26,8 @@ using namespace qldpc;
 struct qldpc_session_s {
     qldpc_code code = nullptr;
     qldpc_decode_params params{};
-    int32_t max_batch = 0;
+    int32_t max_batch = 0;          // shots
+    int32_t unit = 1;               // shots per request item: 2 for a CSS pair session
     int32_t io_mode = 0;
     int32_t syn_words = 0, err_words = 0;
     size_t prior_bytes_per_shot = 0;
@@ -245,12 +246,10 @@ qldpc_status run_staged(qldpc_session s, int32_t batch) {
     return QLDPC_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *params, int32_t max_batch,
-                                  int32_t io_mode, qldpc_session *out) {
+// A session over `max_batch` shots; code_x (CSS pairs, resident only): the
+// H_X side, decoding the odd shots.
+qldpc_status session_create_impl(qldpc_code code, qldpc_code code_x, const qldpc_decode_params *params,
+                                 int32_t max_batch, int32_t io_mode, qldpc_session *out) {
     if (!code || !params || !out) return set_error(QLDPC_ERR_INVALID_ARG, "session_create: null argument");
     if (max_batch <= 0) return set_error(QLDPC_ERR_INVALID_ARG, "session_create: max_batch must be positive");
     if (io_mode != QLDPC_IO_COPY && io_mode != QLDPC_IO_MAPPED && io_mode != QLDPC_IO_RESIDENT)
@@ -272,6 +271,7 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
     s->code = code;
     s->params = *params;
     s->max_batch = max_batch;
+    s->unit = code_x ? 2 : 1;
     s->io_mode = io_mode;
     s->syn_words = (code->m + 31) / 32;
     s->err_words = (code->n + 31) / 32;
@@ -322,7 +322,9 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
     if (resident) {
         s->rkey = k;
         s->rkey.post = 0;
+        if (code_x) s->rkey.which = 2;
         s->rargs.a = a;
+        s->rargs.code_x = code_x ? code_x->dev : nullptr;
         s->rargs.a.syn = s->m_syn;
         s->rargs.a.prior = s->m_prior;
         s->rargs.a.err = s->m_err;
@@ -343,6 +345,30 @@ qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *pa
     return QLDPC_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *params, int32_t max_batch,
+                                  int32_t io_mode, qldpc_session *out) {
+    return session_create_impl(code, nullptr, params, max_batch, io_mode, out);
+}
+
+qldpc_status qldpc_session_create_css(qldpc_code hz_side, qldpc_code hx_side, const qldpc_decode_params *params,
+                                      int32_t max_pairs, qldpc_session *out) {
+    if (!hz_side || !hx_side || !params || !out) return set_error(QLDPC_ERR_INVALID_ARG, "session_create_css: null argument");
+    if (max_pairs <= 0 || 2 * max_pairs > kMaxResident)
+        return set_error(QLDPC_ERR_INVALID_ARG, "session_create_css: max_pairs must be in [1, 32]");
+    if (hz_side->which != 0 || hx_side->which != 1)
+        return set_error(QLDPC_ERR_INVALID_ARG, "session_create_css: needs an H_Z-pattern and an H_X-pattern code");
+    if (hz_side->L != hx_side->L || hz_side->m != hx_side->m || hz_side->n != hx_side->n ||
+        hz_side->device != hx_side->device)
+        return set_error(QLDPC_ERR_INVALID_ARG, "session_create_css: the two sides differ in lift, size or device");
+    if (params->fmt != QLDPC_F32 && params->fmt != QLDPC_I8Q4)
+        return set_error(QLDPC_ERR_UNSUPPORTED, "session_create_css: FP32 or int8 messages");
+    return session_create_impl(hz_side, hx_side, params, 2 * max_pairs, QLDPC_IO_RESIDENT, out);
+}
+
 qldpc_status qldpc_session_destroy(qldpc_session s) {
     if (!s) return QLDPC_OK;
     if (!resident_stop(s))   // leave the buffers to a grid that still runs rather than free them under it
@@ -356,8 +382,10 @@ qldpc_status qldpc_session_decode(qldpc_session s, int32_t batch, const uint32_t
                                   const void *host_prior, uint32_t *host_err, uint8_t *host_conv,
                                   uint8_t *host_iters) {
     if (!s) return set_error(QLDPC_ERR_INVALID_ARG, "session_decode: null session");
-    if (batch < 0 || batch > s->max_batch) return set_error(QLDPC_ERR_INVALID_ARG, "session_decode: batch out of range");
+    if (batch < 0 || batch > s->max_batch / s->unit)
+        return set_error(QLDPC_ERR_INVALID_ARG, "session_decode: batch out of range");
     if (batch == 0) return QLDPC_OK;
+    batch *= s->unit;   // shots
     if (!host_syn || !host_prior) return set_error(QLDPC_ERR_INVALID_ARG, "session_decode: null input");
     std::memcpy(s->h_syn, host_syn, (size_t)batch * s->syn_words * 4);
     std::memcpy(s->h_prior, host_prior, (size_t)batch * s->prior_bytes_per_shot);
@@ -372,17 +400,18 @@ qldpc_status qldpc_session_decode(qldpc_session s, int32_t batch, const uint32_t
 qldpc_status qldpc_session_latency(qldpc_session s, int32_t nreq, int32_t batch, int32_t pool,
                                    const uint32_t *host_syn, const void *host_prior, double *lat_us) {
     if (!s || !host_syn || !host_prior || !lat_us) return set_error(QLDPC_ERR_INVALID_ARG, "session_latency: null argument");
-    if (nreq < 0 || batch <= 0 || batch > s->max_batch || pool < batch)
+    if (nreq < 0 || batch <= 0 || batch > s->max_batch / s->unit || pool < batch)
         return set_error(QLDPC_ERR_INVALID_ARG, "session_latency: bad sizes");
-    std::vector<uint32_t> err((size_t)batch * s->err_words);
-    std::vector<uint8_t> conv(batch), it(batch);
+    const int64_t u = s->unit;   // shots per item
+    std::vector<uint32_t> err((size_t)(batch * u) * s->err_words);
+    std::vector<uint8_t> conv(batch * u), it(batch * u);
     const char *pr = static_cast<const char *>(host_prior);
     for (int32_t i = 0; i < nreq; ++i) {
         int64_t start = ((int64_t)i * batch) % pool;
         if (start + batch > pool) start = 0;
         const auto t0 = std::chrono::steady_clock::now();
-        qldpc_status st = qldpc_session_decode(s, batch, host_syn + start * s->syn_words,
-                                               pr + start * s->prior_bytes_per_shot, err.data(), conv.data(),
+        qldpc_status st = qldpc_session_decode(s, batch, host_syn + start * u * s->syn_words,
+                                               pr + start * u * s->prior_bytes_per_shot, err.data(), conv.data(),
                                                it.data());
         const auto t1 = std::chrono::steady_clock::now();
         if (st != QLDPC_OK) return st;

@@ -111,3 +111,59 @@ def test_mixed_batch_decodes_both_sides_together():
         g = gpu_decode(decs[c], mb.s[c], mb.gamma[idx], posterior=False)
         assert np.array_equal(e_all[c], g[0]), (L, w)
         assert np.array_equal(conv_h[idx], g[1]) and np.array_equal(it_h[idx], g[2]), (L, w)
+
+
+@pytest.mark.parametrize("L,fmt,nw", [(64, 0, 16), (64, 1, 8), (128, 0, 16)])
+def test_css_pair_resident_session(L, fmt, nw):
+    """One request decodes both sides of a CSS code: the H_Z syndrome of X
+    errors and the H_X syndrome of independent Z errors, each against the
+    oracle on its own parity-check matrix, for one pair and for several."""
+    c, hz, Hz, dz = side(L, 0)
+    _, hx, Hx, dx = side(L, 1)
+    n = 20
+    bz = noise.Batch(hz, 501 + L, np.arange(n), 0.05)
+    bx = noise.Batch(hx, 601 + L, np.arange(n), 0.03)
+    pz = bz.gamma if fmt == 0 else bz.gamma_q4()
+    px = bx.gamma if fmt == 0 else bx.gamma_q4()
+    oz = oracle_decode(Hz, bz.s, pz, fmt=fmt)
+    ox = oracle_decode(Hx, bx.s, px, fmt=fmt)
+    # pairs: [n][2][...], H_Z side first
+    syn = np.ascontiguousarray(np.stack([bits.pack_bits(bz.s), bits.pack_bits(bx.s)], axis=1).reshape(2 * n, -1))
+    prior = np.ascontiguousarray(np.stack([pz, px], axis=1).reshape(2 * n))
+    s = abi.qldpc_session_create_css(dz.handle, dx.handle, dz.params(fmt=fmt, waves_per_shot=nw), 8)
+    try:
+        for lo, hi in ((0, 1), (1, 9), (9, 12), (12, 20)):
+            B = hi - lo
+            err = np.zeros((2 * B, dz.err_words), np.uint32)
+            conv = np.full(2 * B, 7, np.uint8)
+            it = np.zeros(2 * B, np.uint8)
+            abi.qldpc_session_decode(s, B, syn[2 * lo:2 * hi], prior[2 * lo:2 * hi], err, conv, it)
+            e = bits.unpack_bits(err, hz.n)
+            assert np.array_equal(e[0::2], oz.e[lo:hi]) and np.array_equal(e[1::2], ox.e[lo:hi]), (lo, hi)
+            assert np.array_equal(conv[0::2], oz.converged[lo:hi]) and np.array_equal(conv[1::2], ox.converged[lo:hi])
+            assert np.array_equal(it[0::2].astype(np.int32), oz.iters[lo:hi])
+            assert np.array_equal(it[1::2].astype(np.int32), ox.iters[lo:hi])
+        lat = abi.qldpc_session_latency(s, 200, 1, n, syn, prior)
+        assert np.all(lat > 0) and np.isfinite(lat).all()
+    finally:
+        abi.qldpc_session_destroy(s)
+
+
+def test_css_pair_session_rejects_bad_pairs():
+    c, hz, Hz, dz = side(64, 0)
+    _, hx, Hx, dx = side(64, 1)
+    _, hx128, _, dx128 = side(128, 1)
+    for a_, b_, kw, mp in ((dx, dz, {}, 4), (dz, dx128, {}, 4), (dz, dx, {}, 33), (dz, dx, {}, 0),
+                           (dz, dx, dict(fmt=abi.QLDPC_I16Q8), 4)):
+        with pytest.raises(abi.QldpcError) as ei:
+            abi.qldpc_session_create_css(a_.handle, b_.handle, dz.params(**kw), mp)
+        assert ei.value.status in (abi.QLDPC_ERR_INVALID_ARG, abi.QLDPC_ERR_UNSUPPORTED)
+    s = abi.qldpc_session_create_css(dz.handle, dx.handle, dz.params(), 2)
+    try:
+        with pytest.raises(abi.QldpcError) as ei:      # 3 pairs > max_pairs
+            abi.qldpc_session_decode(s, 3, np.zeros((6, dz.syn_words), np.uint32), np.ones(6, np.float32),
+                                     np.zeros((6, dz.err_words), np.uint32), np.zeros(6, np.uint8),
+                                     np.zeros(6, np.uint8))
+        assert ei.value.status == abi.QLDPC_ERR_INVALID_ARG
+    finally:
+        abi.qldpc_session_destroy(s)
