@@ -230,6 +230,42 @@ __device__ __forceinline__ int sat(int x) {
     return min(Q, max(-Q, x));
 }
 
+// ---- integer formats on integer-valued FP32 lanes (register layout) -------
+// Every value of the integer formats is an integer of magnitude below 2^24
+// (|Q| <= qmax + 5 (3 qmax >> 2) < 2^18), so FP32 holds it, and sums and
+// differences of such values, exactly.  alpha = num / 2^sh with num * |q| <
+// 2^24, so fl(alpha * min) is exact and its floor is (num * min) >> sh.  The
+// same values as cn_fx and sat, bit for bit, on the FP32 instructions, whose
+// abs and negate operand modifiers the integer instructions lack.  No value
+// is ever -0.0 (sums start from a converted integer prior), so the sign bit of
+// q is [q < 0].
+template <int DC>
+__device__ __forceinline__ void cn_fxf(float (&v)[DC], uint32_t P, float alpha) {
+    float m1 = fminf(fabsf(v[0]), fabsf(v[1]));
+    float m2 = fmaxf(fabsf(v[0]), fabsf(v[1]));
+#pragma unroll
+    for (int j = 2; j < DC; ++j) {
+        m2 = __builtin_amdgcn_fmed3f(m1, m2, fabsf(v[j]));
+        m1 = fminf(m1, fabsf(v[j]));
+    }
+#pragma unroll
+    for (int j = 0; j < DC; ++j) P ^= fbits(v[j]);
+    float A1 = floorf(alpha * m1);
+    float A2 = floorf(alpha * m2);
+    asm volatile("" : "+v"(A1), "+v"(A2));
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        const float mag = (fabsf(v[j]) == m1) ? A2 : A1;
+        v[j] = ubits(fbits(mag) | ((P ^ fbits(v[j])) & 0x80000000u));
+    }
+}
+
+template <int FMT>
+__device__ __forceinline__ float satf(float x) {
+    constexpr float Q = (float)Fmt<FMT>::qmax;
+    return __builtin_amdgcn_fmed3f(-Q, x, Q);
+}
+
 // The value of lane 0, as a wave-uniform (scalar) value.
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -321,7 +357,9 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
     using msg_t = typename Fmt<FMT>::msg_t;
     using q_t = typename Fmt<FMT>::q_t;
     using prior_t = typename Fmt<FMT>::prior_t;
-    using acc_t = typename std::conditional<FMT == 0, float, int>::type;
+    // REG: integer formats run on integer-valued FP32 lanes (cn_fxf, satf)
+    constexpr bool FXF = REG && FMT != 0;
+    using acc_t = typename std::conditional<FMT == 0 || FXF, float, int>::type;
     static_assert(L <= 64 || NG == 1, "L = 128 uses both halves for one shot");
     static_assert(!REG || (L <= 64 && NG == 1 && !(WEIGHTED && (SCHED == 1 || FMT != 0))),
                   "register-resident messages: L <= 64, one group");
@@ -497,6 +535,13 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                             if constexpr (REG) m[R * DC + j] = v[j];
                             else msg[(R * DC + j) * ROW + lane + 64 * h] = v[j];
                         }
+                    } else if constexpr (FXF) {
+                        float v[DC];
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) v[j] = m[R * DC + j];
+                        cn_fxf<DC>(v, P, a.alpha);
+#pragma unroll
+                        for (int j = 0; j < DC; ++j) m[R * DC + j] = v[j];
                     } else {
                         int v[DC];
 #pragma unroll
@@ -527,10 +572,10 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                         // Q of the variable (C, t + s) this lane's check sees, minus the old r
                         v[j] = bperm(cn_src(shift_of(R * DC + j)), Qv[C]) - m[R * DC + j];
                         if constexpr (FMT == 0) c[j] = v[j];
-                        else c[j] = sat<FMT>(v[j]);      // check-node input
+                        else c[j] = satf<FMT>(v[j]);     // check-node input
                     });
                     if constexpr (FMT == 0) cn_f32<DC>(c, P, a.alpha);
-                    else cn_fx<DC>(c, P, a.alpha_num, a.alpha_shift);
+                    else cn_fxf<DC>(c, P, a.alpha);
                     static_for<0, DC>([&](auto Jc) {
                         constexpr int j = decltype(Jc)::value;
                         constexpr int C = S::T.slot_bc[R][j];
@@ -651,6 +696,17 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                                 for (int i = 0; i < d; ++i) msg[idx[i]] = qv[i];
                             }
                             Q = pre[d];
+                        } else if constexpr (FXF) {
+                            // exact integer values: Q - r form
+                            float sum = gamma_of(C, h);
+#pragma unroll
+                            for (int i = 0; i < d; ++i) sum += r[i];
+                            static_for<0, d>([&](auto Ii) {
+                                constexpr int i = decltype(Ii)::value;
+                                constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
+                                m[slot] = bperm(cn_src(shift_of(slot)), satf<FMT>(sum - r[i]));
+                            });
+                            Q = sum;
                         } else {
                             int sum = gamma_of(C, h);
 #pragma unroll
