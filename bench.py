@@ -377,6 +377,7 @@ def main():
 
     # ---------------- CPU oracle on a bounded sample ---------------------------
     cpu = None
+    cpu_detail = None
     if not args.no_cpu:
         import oracle
         nthr = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -391,6 +392,22 @@ def main():
         cpu = dict(value=S * len(P_LIST) / dt, unit="syndromes/s", cores=int(nthr), kind="oracle",
                    sample=f"first {S} shots of each of the 3 batches (p=0.01,0.03,0.05), "
                           f"FP32 flooding, 32 iterations, early stop; {dt:.2f} s wall")
+        # the same oracle on one thread (a smaller sample), and the host CPU
+        S1 = max(1, S // 32)
+        t = time.perf_counter()
+        for s_, g_ in samples:
+            oracle.flood_f32(H, s_[:S1], g_[:S1], alpha=0.75, max_iters=32, early_stop=True, nthreads=1)
+        dt1 = time.perf_counter() - t
+        model = None
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        cpu_detail = dict(single_thread=S1 * len(P_LIST) / dt1, single_thread_sample=f"first {S1} shots of each batch",
+                          threads=int(nthr), cpu_model=model, unit="syndromes/s")
 
     out = {
         "metric": METRIC,
@@ -440,6 +457,7 @@ def main():
         "large_lift_hbm": hbm,
         "pcie_inclusive": pcie,
         "cpu_baseline": cpu,
+        "cpu_oracle_detail": cpu_detail,
         "ler": ler,
         "variants": variants,
         "input_generation_s": gen_s,
