@@ -185,3 +185,23 @@ def test_resident_session_rejects_unsupported_configs():
         with pytest.raises(abi.QldpcError) as ei:
             abi.qldpc_session_create(dec.handle, dec.params(**kw), mb, abi.QLDPC_IO_RESIDENT)
         assert ei.value.status == status, (L, kw, mb)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_auto_layout_at_L128_large_batch(fmt):
+    """AUTO at L = 128 with a large batch takes 8-wave workgroups with messages
+    in LDS and asks for no workspace; a sample of the batch equals the oracle
+    and the explicit workgroup layout bit for bit."""
+    c, H, dec = code(128)
+    B = 600
+    b = noise.Batch(c.hz, 77 + fmt, np.arange(B), 0.05)
+    prior = b.gamma if fmt == 0 else b.gamma_q4()
+    assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(fmt=fmt), B) == 0
+    g_auto = gpu_decode(dec, b.s, prior, fmt=fmt, layout=abi.QLDPC_LAYOUT_AUTO)
+    g_blk = gpu_decode(dec, b.s, prior, fmt=fmt, layout=abi.QLDPC_LAYOUT_BLOCK, waves_per_shot=8)
+    for x, y in zip(g_auto, g_blk):
+        assert np.array_equal(x, y)
+    idx = np.arange(0, B, 7)
+    o = oracle_decode(H, b.s[idx], prior[idx], fmt=fmt)
+    sub = tuple(x[idx] for x in g_auto)
+    assert_parity(sub, o, b.gamma[idx][:, None] if fmt == 0 else None, fmt, tag=f"AUTO L=128 fmt={fmt}")
