@@ -43,7 +43,7 @@ def _p(a):
 
 def _declare(L):
     vp, i32, f32 = C.c_void_p, C.c_int, C.c_float
-    L.orc_flood_f32.argtypes = [i32, i32, vp, i32, vp, vp, f32, vp, i32, i32, vp, vp, vp, vp, vp, vp, i32]
+    L.orc_flood_f32.argtypes = [i32, i32, vp, i32, vp, vp, f32, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, i32]
     L.orc_flood_i8.argtypes = [i32, i32, vp, i32, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, i32]
     L.orc_layered_f32.argtypes = [i32, i32, vp, i32, vp, vp, f32, i32, vp, i32, i32, vp, vp, vp, vp, i32]
     L.orc_layered_i8.argtypes = [i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, i32, i32, vp, vp, vp, vp, i32]
@@ -87,7 +87,11 @@ class Result:
 
 def flood_f32(H, syn, prior, alpha=0.75, max_iters=32, early_stop=True, weights=None,
               want_Q_all=False, want_q_traj=False, nthreads=None):
-    """Flooding min-sum, FP32.  prior: scalar, [B] per shot or [B, n]."""
+    """Flooding min-sum, FP32.  prior: scalar, [B] per shot or [B, n].
+
+    weights [T][nnz] (T <= max_iters) replace alpha in iterations 1..T;
+    iterations T+1..max_iters use alpha (neural min-sum, then plain min-sum
+    continuing from its messages)."""
     H, syn = _prep(H, syn)
     m, n = H.shape
     B = syn.shape[0]
@@ -95,7 +99,7 @@ def flood_f32(H, syn, prior, alpha=0.75, max_iters=32, early_stop=True, weights=
     nnz = int(lib().orc_edge_count(m, n, _p(H)))
     w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
     if w is not None:
-        assert w.shape == (max_iters, nnz)
+        assert w.ndim == 2 and w.shape[1] == nnz and 1 <= w.shape[0] <= max_iters
     e = np.zeros((B, n), np.uint8)
     conv = np.zeros(B, np.uint8)
     it = np.zeros(B, np.int32)
@@ -103,6 +107,7 @@ def flood_f32(H, syn, prior, alpha=0.75, max_iters=32, early_stop=True, weights=
     Qa = np.zeros((max_iters, B, n), np.float32) if want_Q_all else None
     qt = np.zeros((max_iters, B, nnz), np.float32) if want_q_traj else None
     rc = lib().orc_flood_f32(m, n, _p(H), B, _p(syn), _p(prior), float(alpha), _p(w),
+                             0 if w is None else int(w.shape[0]),
                              int(max_iters), int(bool(early_stop)), _p(e), _p(conv), _p(it),
                              _p(Q), _p(Qa), _p(qt), _threads(nthreads))
     assert rc == 0

@@ -191,13 +191,15 @@ static inline int prior_at(const void *p, fxfmt_t f, long i) {
 
 /* ---------------------------------------------------------------------- */
 /* Flooding schedule, FP32 (Algorithm 1).  Optional per-iteration weights   */
-/* w[k-1][e] replace alpha (neural min-sum).  Optional outputs: final       */
+/* w[k-1][e] replace alpha (neural min-sum) in iterations k <= wT; later    */
+/* iterations use alpha (plain min-sum continuing from the neural state,    */
+/* the continuation fallback).  Optional outputs: final                     */
 /* posterior Q [B][n], every iteration's posterior Q_all [iters][B][n], and */
 /* the inputs of every check-node pass q_traj [iters][B][nnz] (q^{(k-1)}).  */
 /* ---------------------------------------------------------------------- */
 int orc_flood_f32(int m, int n, const uint8_t *H, int nshots,
                   const uint8_t *syn, const float *prior, float alpha,
-                  const float *w, int max_iters, int early_stop,
+                  const float *w, int wT, int max_iters, int early_stop,
                   uint8_t *e_out, uint8_t *conv, int32_t *iters,
                   float *Q_out, float *Q_all, float *q_traj, int nthreads) {
     graph_t g;
@@ -217,7 +219,7 @@ int orc_flood_f32(int m, int n, const uint8_t *H, int nshots,
         int done = 0, k;
         for (k = 1; k <= max_iters; k++) {
             if (q_traj) memcpy(q_traj + ((long)(k - 1) * nshots + b) * nnz, q, sizeof(float) * nnz);
-            const float *wk = w ? w + (long)(k - 1) * nnz : NULL;
+            const float *wk = (w && k <= wT) ? w + (long)(k - 1) * nnz : NULL;
             for (int r = 0; r < m; r++) cn_f32(&g, r, s[r] & 1, q, rr, alpha, wk);
             /* variable nodes: excluded sums in increasing check order */
             for (int c = 0; c < n; c++) {

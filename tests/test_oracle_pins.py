@@ -354,6 +354,36 @@ def test_neural_with_alpha_weights_is_alpha_ms():
     assert np.allclose(Qd, ra.Q_all, rtol=1e-5, atol=1e-5 * np.abs(b.gamma).max())
 
 
+def test_neural_then_plain_continuation():
+    """Weights for the first T of I_max iterations: with w = alpha it is plain
+    min-sum bit for bit; the first T iterations are the neural decoder's, and
+    the iterations after T apply alpha (checked against the double-precision
+    neural forward, whose weights are alpha beyond T)."""
+    c = lp.lp_code(16)
+    H = c.hz.dense()
+    b = noise.Batch(c.hz, 14, np.arange(30), 0.06)
+    T, I = 3, 9
+    wa = np.full((T, c.hz.nnz), 0.75, np.float32)
+    ra = oracle.flood_f32(H, b.s, b.gamma, max_iters=I, early_stop=False, want_Q_all=True)
+    rw = oracle.flood_f32(H, b.s, b.gamma, weights=wa, max_iters=I, early_stop=False, want_Q_all=True)
+    assert np.array_equal(ra.Q_all, rw.Q_all)
+    rng = np.random.default_rng(5)
+    w = rng.uniform(0.4, 1.0, size=(T, c.hz.nnz)).astype(np.float32)
+    rn = oracle.flood_f32(H, b.s, b.gamma, weights=w, max_iters=T, early_stop=False, want_Q_all=True)
+    rc = oracle.flood_f32(H, b.s, b.gamma, weights=w, max_iters=I, early_stop=False, want_Q_all=True)
+    assert np.array_equal(rc.Q_all[:T], rn.Q_all)
+    wfull = np.concatenate([w, np.full((I - T, c.hz.nnz), 0.75, np.float32)]).astype(np.float64)
+    Qd, _ = oracle.nms_forward_f64(H, b.s, b.gamma.astype(np.float64), wfull)
+    assert np.allclose(Qd, rc.Q_all, rtol=1e-5, atol=1e-5 * np.abs(b.gamma).max())
+    # with early stop, the reported iteration is the first whose decision satisfies s
+    re = oracle.flood_f32(H, b.s, b.gamma, weights=w, max_iters=I, early_stop=True)
+    ok = re.converged == 1
+    assert np.array_equal(noise.syndromes(c.hz, re.e[ok]), b.s[ok])
+    for i in np.nonzero(ok)[0][:10]:
+        k = int(re.iters[i])
+        assert np.array_equal(rc.Q_all[k - 1, i] < 0, re.e[i].astype(bool))
+
+
 def test_neural_adjoint_matches_finite_differences():
     rng = np.random.default_rng(21)
     c = lp.lp_code(16)
