@@ -388,6 +388,18 @@ qldpc_status qldpc_nbp_decode(qldpc_code code, int32_t batch, int32_t T, const f
                               const float *priors, uint32_t *errors, uint8_t *converged,
                               uint8_t *iters_used, uint8_t *used_fallback, void *stream);
 
+/* Inference with a continuing fallback: neural min-sum (weights [T][nnz])
+ * in iterations 1..T, then plain min-sum with `alpha` continuing from the
+ * neural decoder's messages in iterations T+1..max_iters (T <= max_iters
+ * <= 255), early stop throughout, in one pass.  iters_used (required) counts
+ * every iteration; used_fallback: device uint8 [batch], out: 1 where plain
+ * iterations ran (iters_used > T).  Same codes and buffers as
+ * qldpc_nbp_decode.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
+qldpc_status qldpc_nbp_decode_continue(qldpc_code code, int32_t batch, int32_t T, const float *weights,
+                                       int32_t max_iters, float alpha, const uint32_t *syndromes,
+                                       const float *priors, uint32_t *errors, uint8_t *converged,
+                                       uint8_t *iters_used, uint8_t *used_fallback, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of decode requests (several asynchronous     */
 /* decoders overlapping copies and kernels, Table 1 and Section 3)           */

@@ -126,6 +126,7 @@ def _load():
         "qldpc_nbp_forward": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], i32),
         "qldpc_nbp_backward": ([vp, i32, i32, vp, vp, vp, vp, vp, vp], i32),
         "qldpc_nbp_decode": ([vp, i32, i32, vp, C.POINTER(qldpc_decode_params), vp, vp, vp, vp, vp, vp, vp], i32),
+        "qldpc_nbp_decode_continue": ([vp, i32, i32, vp, i32, C.c_float, vp, vp, vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -311,6 +312,13 @@ def qldpc_nbp_decode(h, batch: int, T: int, weights, fallback, syndromes, priors
     _check(lib.qldpc_nbp_decode(h, int(batch), int(T), _ptr(weights), fb, _ptr(syndromes), _ptr(priors),
                                 _ptr(errors), _ptr(converged), _ptr(iters_used), _ptr(used_fallback),
                                 _stream(stream)))
+
+
+def qldpc_nbp_decode_continue(h, batch: int, T: int, weights, max_iters: int, alpha: float, syndromes, priors,
+                              errors, converged, iters_used, used_fallback, stream=None) -> None:
+    _check(lib.qldpc_nbp_decode_continue(h, int(batch), int(T), _ptr(weights), int(max_iters), float(alpha),
+                                         _ptr(syndromes), _ptr(priors), _ptr(errors), _ptr(converged),
+                                         _ptr(iters_used), _ptr(used_fallback), _stream(stream)))
 
 
 def qldpc_mixed_create(handles, params: qldpc_decode_params, max_batch: int, use_graph: bool = True):

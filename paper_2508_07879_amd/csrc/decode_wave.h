@@ -524,9 +524,13 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                         for (int j = 0; j < DC; ++j)
                             v[j] = REG ? m[R * DC + j] : msg[(R * DC + j) * ROW + lane + 64 * h];
                         if constexpr (WEIGHTED) {
-                            float wj[DC];
-                            load_weights<L, DC>(a.weights, k - 1, MB * L * DC, R, p + posoff(h), wj);
-                            cn_f32_weighted<DC>(v, P, wj);
+                            if (k <= a.weight_iters) {   // uniform: neural iterations, then plain
+                                float wj[DC];
+                                load_weights<L, DC>(a.weights, k - 1, MB * L * DC, R, p + posoff(h), wj);
+                                cn_f32_weighted<DC>(v, P, wj);
+                            } else {
+                                cn_f32<DC>(v, P, a.alpha);
+                            }
                         } else {
                             cn_f32<DC>(v, P, a.alpha);
                         }

@@ -40,7 +40,8 @@ struct DecodeArgs {
     int32_t alpha_num;      // I8Q4: alpha = alpha_num / 2^alpha_shift
     int32_t alpha_shift;
     const uint8_t *only;    // nullable: decode only shots with only[shot] != 0
-    const float *weights;   // neural decode: [max_iters][nnz] per-edge scales
+    const float *weights;   // neural decode: [weight_iters][nnz] per-edge scales
+    int32_t weight_iters;   // neural decode: iterations 1..weight_iters use the weights, later ones alpha
 };
 
 // Doorbell page of a resident decoder, in mapped (fine-grained) host memory.

@@ -73,6 +73,10 @@ __global__ void k_not(const uint8_t *conv, uint8_t *out, int32_t n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = conv[i] ? 0 : 1;
 }
+__global__ void k_beyond(const uint8_t *iters, int32_t T, uint8_t *out, int32_t n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = iters[i] > T ? 1 : 0;
+}
 
 }  // namespace
 
@@ -167,6 +171,7 @@ qldpc_status qldpc_nbp_decode(qldpc_code code, int32_t batch, int32_t T, const f
     d.early_stop = 1;
     d.alpha = 1.0f;
     d.weights = weights;
+    d.weight_iters = T;
     st = result(launch(code, 3, NmsArgs{}, d, s), "nbp_decode: neural pass");
     if (st != QLDPC_OK) return st;
     hipLaunchKernelGGL(k_not, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, converged, used_fallback, batch);
@@ -185,6 +190,41 @@ qldpc_status qldpc_nbp_decode(qldpc_code code, int32_t batch, int32_t T, const f
     f.only = used_fallback;
     k.post = 0;
     return result(launch_decode(k, f, s), "nbp_decode: fallback pass");
+}
+
+qldpc_status qldpc_nbp_decode_continue(qldpc_code code, int32_t batch, int32_t T, const float *weights,
+                                       int32_t max_iters, float alpha, const uint32_t *syn, const float *priors,
+                                       uint32_t *errors, uint8_t *converged, uint8_t *iters_used,
+                                       uint8_t *used_fallback, void *stream) {
+    qldpc_status st = check(code, batch, T);
+    if (st != QLDPC_OK || batch == 0) return st;
+    if (max_iters < T || max_iters > 255)
+        return set_error(QLDPC_ERR_INVALID_ARG, "nbp_decode_continue: max_iters must be in [T, 255]");
+    if (!(alpha > 0.0f && alpha <= 1.0f)) return set_error(QLDPC_ERR_INVALID_ARG, "nbp_decode_continue: alpha must be in (0, 1]");
+    if (!weights || !syn || !priors || !errors || !converged || !iters_used || !used_fallback)
+        return set_error(QLDPC_ERR_INVALID_ARG, "nbp_decode_continue: null buffer");
+    if (((uintptr_t)weights & 15) != 0)
+        return set_error(QLDPC_ERR_INVALID_ARG, "nbp_decode_continue: weights must be 16-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    // one pass: weights in iterations 1..T, alpha after, early stop throughout
+    DecodeArgs d{};
+    d.code = code->dev;
+    d.syn = syn;
+    d.prior = priors;
+    d.err = errors;
+    d.conv = converged;
+    d.iters = iters_used;
+    d.batch = batch;
+    d.max_iters = max_iters;
+    d.early_stop = 1;
+    d.alpha = alpha;
+    d.weights = weights;
+    d.weight_iters = T;
+    st = result(launch(code, 3, NmsArgs{}, d, s), "nbp_decode_continue");
+    if (st != QLDPC_OK) return st;
+    hipLaunchKernelGGL(k_beyond, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, iters_used, T, used_fallback,
+                       batch);
+    return result(hipGetLastError(), "nbp_decode_continue: mark");
 }
 
 }  // extern "C"

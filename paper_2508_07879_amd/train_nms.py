@@ -146,6 +146,7 @@ def _evaluate(args, code, side, dec, dev, w, T, report):
     for t in sorted({max(1, T // 4), T // 2, (3 * T) // 4, T}):
         configs.append((f"nms_T{t}", "nms", t, True))
         configs.append((f"nms_T{t}_nofallback", "nms", t, False))
+        configs.append((f"nms_T{t}_continue", "nmsc", t, True))
     configs += [("ms_16", "ms", 16, False), ("ms_32", "ms", 32, False)]
     for t in sorted({max(1, T // 4), T // 2, (3 * T) // 4}):
         configs.append((f"ms_{t}", "ms", t, False))
@@ -163,6 +164,9 @@ def _evaluate(args, code, side, dec, dev, w, T, report):
             if kind == "nms":
                 fbp = dec.params(max_iters=32) if fb else None
                 abi.qldpc_nbp_decode(dec.handle, B, t, wd[:t].contiguous(), fbp, syn, pr, err, conv, it, used)
+            elif kind == "nmsc":   # plain min-sum continues from the neural messages up to 32 iterations
+                abi.qldpc_nbp_decode_continue(dec.handle, B, t, wd[:t].contiguous(), 32, 0.75, syn, pr, err, conv,
+                                              it, used)
             else:
                 prm = dec.params(max_iters=t)
                 abi.qldpc_decode_batch(dec.handle, prm, B, syn, pr, err, conv, it, None)
@@ -173,7 +177,7 @@ def _evaluate(args, code, side, dec, dev, w, T, report):
             st["fails"] += logical_fail_counts(lam_t, et, err, conv, side.n)
             st["shots"] += B
             st["iters"] += int(it.to(torch.int64).sum().item())
-            if kind == "nms":
+            if kind in ("nms", "nmsc"):
                 st["fallback"] += int(used.to(torch.int64).sum().item())
     res = {}
     for name, st in stats.items():

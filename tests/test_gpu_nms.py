@@ -142,3 +142,30 @@ def test_inference_with_fallback(L, p):
     assert np.array_equal(used.cpu().numpy(), fall.astype(np.uint8))
     assert np.array_equal(e, want_e) and np.array_equal(conv.cpu().numpy(), want_c)
     assert np.array_equal(it.cpu().numpy().astype(np.int32), want_i)
+
+
+@pytest.mark.parametrize("L,p", [(32, 0.06), (64, 0.04), (128, 0.04)])
+def test_inference_with_continuing_fallback(L, p):
+    """Neural weights in iterations 1..T, plain min-sum continuing from the
+    neural messages up to 32 iterations: decisions, flags and iteration counts
+    equal the oracle's, and the fallback flag marks iterations beyond T."""
+    c, H, dec = code(L)
+    b = noise.Batch(c.hz, 45, np.arange(160 if L < 128 else 64), p)
+    T = 8
+    w = np.random.default_rng(8).uniform(0.6, 0.9, size=(T, c.hz.nnz)).astype(np.float32)
+    syn = to_dev(bits.pack_bits(b.s).view(np.int32))
+    pr = to_dev(b.gamma)
+    err, conv, it, _ = dec.outputs(b.B)
+    used = torch.empty(b.B, dtype=torch.uint8, device="cuda")
+    abi.qldpc_nbp_decode_continue(dec.handle, b.B, T, to_dev(w), 32, 0.75, syn, pr, err, conv, it, used)
+    torch.cuda.synchronize()
+    e = bits.unpack_bits(err.cpu().numpy().view(np.uint32), c.n)
+    o = oracle.flood_f32(H, b.s, b.gamma, weights=w, max_iters=32, early_stop=True)
+    its = it.cpu().numpy().astype(np.int32)
+    assert np.array_equal(e, o.e) and np.array_equal(conv.cpu().numpy(), o.converged)
+    assert np.array_equal(its, o.iters)
+    assert np.array_equal(used.cpu().numpy(), (o.iters > T).astype(np.uint8))
+    assert (o.iters > T).any() and (o.iters <= T).any()
+    with pytest.raises(abi.QldpcError) as ei:          # max_iters below T
+        abi.qldpc_nbp_decode_continue(dec.handle, b.B, T, to_dev(w), T - 1, 0.75, syn, pr, err, conv, it, used)
+    assert ei.value.status == abi.QLDPC_ERR_INVALID_ARG
