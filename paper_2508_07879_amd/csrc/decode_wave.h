@@ -348,7 +348,10 @@ struct ShotRef {
 // the order of every operation are those of the LDS form; only where the
 // messages are kept differs.
 // ---------------------------------------------------------------------------
-template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED, int NG, bool REG = false>
+// WEIGHTED: 0 = alpha; 1 = per-edge weights in every iteration (neural
+// min-sum); 2 = weights in iterations 1..a.weight_iters, alpha after (plain
+// min-sum continuing from the neural messages).
+template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, int WEIGHTED, int NG, bool REG = false>
 __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *__restrict__ code,
                                             const ShotRef (&ref)[NG], unsigned char *lds) {
     using namespace wave;
@@ -523,7 +526,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
 #pragma unroll
                         for (int j = 0; j < DC; ++j)
                             v[j] = REG ? m[R * DC + j] : msg[(R * DC + j) * ROW + lane + 64 * h];
-                        if constexpr (WEIGHTED) {
+                        if constexpr (WEIGHTED == 2) {
                             if (k <= a.weight_iters) {   // uniform: neural iterations, then plain
                                 float wj[DC];
                                 load_weights<L, DC>(a.weights, k - 1, MB * L * DC, R, p + posoff(h), wj);
@@ -531,6 +534,10 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                             } else {
                                 cn_f32<DC>(v, P, a.alpha);
                             }
+                        } else if constexpr (WEIGHTED == 1) {
+                            float wj[DC];
+                            load_weights<L, DC>(a.weights, k - 1, MB * L * DC, R, p + posoff(h), wj);
+                            cn_f32_weighted<DC>(v, P, wj);
                         } else {
                             cn_f32<DC>(v, P, a.alpha);
                         }
@@ -870,7 +877,7 @@ __device__ __forceinline__ long xcd_wave_index(long b, long G) {
 }
 
 // One wave per workgroup; grid = ceil(batch / shots-per-wave).
-template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, bool WEIGHTED = false>
+template <class S, int L, int FMT, int SCHED, bool PER_BIT, bool POST, int WEIGHTED = 0>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occupancy<S, L, FMT, SCHED>())))
 void k_wave(const DecodeArgs a) {
     using G = Geo<S, L>;
@@ -891,10 +898,10 @@ void k_wave(const DecodeArgs a) {
 // three waves per SIMD (168 VGPRs; the only spills are outside the iteration
 // loop; with per-edge weights a few reloads per iteration, still faster than
 // two waves); per-bit priors or posteriors need two (256 VGPRs).
-template <bool PER_BIT, bool POST, bool WEIGHTED, int SCHED = 0>
+template <bool PER_BIT, bool POST, int WEIGHTED, int SCHED = 0>
 constexpr int reg_waves() { return (!PER_BIT && !POST) ? 3 : 2; }
 
-template <class S, int L, bool PER_BIT, bool POST, bool WEIGHTED = false, int SCHED = 0, int FMT = 0>
+template <class S, int L, bool PER_BIT, bool POST, int WEIGHTED = 0, int SCHED = 0, int FMT = 0>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(reg_waves<PER_BIT, POST, WEIGHTED, SCHED>())))
 void k_wreg(const DecodeArgs a) {
     using G = Geo<S, L>;
@@ -914,7 +921,10 @@ template <class S, int L>
 hipError_t launch_wreg_weighted(const DecodeArgs &a, hipStream_t st) {
     using G = Geo<S, L>;
     const unsigned grid = (unsigned)((a.batch + G::SPW - 1) / G::SPW);
-    hipLaunchKernelGGL((k_wreg<S, L, false, false, true>), dim3(grid), dim3(64), 0, st, a);
+    if (a.weight_iters < a.max_iters)   // neural, then plain iterations
+        hipLaunchKernelGGL((k_wreg<S, L, false, false, 2>), dim3(grid), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_wreg<S, L, false, false, 1>), dim3(grid), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -19,8 +19,12 @@ hipError_t launch_nms_L128(int op, const NmsArgs &n, const DecodeArgs &d, hipStr
             break;
         }
         case 3:
-            hipLaunchKernelGGL((k_wave<S, 128, 0, 0, false, false, true>),
-                               dim3((unsigned)((d.batch + G::SPW - 1) / G::SPW)), dim3(64), 0, st, d);
+            if (d.weight_iters < d.max_iters)   // neural, then plain iterations
+                hipLaunchKernelGGL((k_wave<S, 128, 0, 0, false, false, 2>),
+                                   dim3((unsigned)((d.batch + G::SPW - 1) / G::SPW)), dim3(64), 0, st, d);
+            else
+                hipLaunchKernelGGL((k_wave<S, 128, 0, 0, false, false, 1>),
+                                   dim3((unsigned)((d.batch + G::SPW - 1) / G::SPW)), dim3(64), 0, st, d);
             break;
         default:
             return hipErrorNotSupported;
