@@ -112,3 +112,32 @@ def test_shape_tables_match_the_lp_construction():
             except abi.QldpcError as e:
                 # without a GPU the only acceptable failure is the device step
                 assert e.status == abi.QLDPC_ERR_DEVICE, str(e)
+
+
+def test_quantize_prior_q8_matches_definition():
+    from paper_2508_07879_amd import abi
+    from workload import noise
+    x = np.array([0.0, -0.0, 1 / 512, -1 / 512, 3.4761, 4.5951, 200.0, -200.0, 127.998, -127.9], np.float32)
+    x = np.concatenate([x, np.random.default_rng(1).normal(0, 8, 1000).astype(np.float32)])
+    q = abi.qldpc_quantize_prior_q8(x)
+    assert q.dtype == np.int16 and np.array_equal(q, noise.quantize_q8(x))
+    assert q[6] == 32767 and q[7] == -32767
+
+
+def test_new_entry_points_validate_before_any_device_call():
+    from paper_2508_07879_amd import abi
+    p = abi.qldpc_default_params()
+    with pytest.raises(abi.QldpcError) as ei:
+        abi.qldpc_session_create_css(None, None, p, 4)
+    assert ei.value.status == abi.QLDPC_ERR_INVALID_ARG
+    with pytest.raises(abi.QldpcError) as ei:
+        abi.qldpc_nbp_decode_continue(None, 4, 8, None, 32, 0.75, None, None, None, None, None, None, stream=0)
+    assert ei.value.status == abi.QLDPC_ERR_INVALID_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
