@@ -440,3 +440,94 @@ def test_neural_adjoint_last_iteration_closed_form():
             sgn = (-1) ** int(b.s[sh, mm]) * np.prod([1 if q[f] >= 0 else -1 for f in others])
             want[ei] += G[T - 1, sh, nn] * sgn * mag
     assert np.allclose(gw[T - 1], want, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("fmt", ["i8", "i16"])
+def test_layered_saturation_closed_form(fmt):
+    """Layered fixed-point schedule with s = 0 and a uniform prior g near the
+    bound, block rows as layers.  In the first sweep every check output is
+    (3 min) >> 2 with min in {g, qmax}, so every r >= (3 g) >> 2.  From the
+    second sweep on, every check input Q - r_old = g + (sum of the other
+    d_v - 1 messages) > qmax, so it saturates to qmax, every output is
+    (3 qmax) >> 2, and with the posterior kept exactly Q_n = g + d_v(n)
+    ((3 qmax) >> 2).  Building Q from the saturated input instead (Q = q + r)
+    would give qmax + ((3 qmax) >> 2) for every bit."""
+    c = lp.lp_code(16)
+    H = c.hz.dense()
+    s = np.zeros((2, c.hz.m), np.uint8)
+    qmax, g, dt, run, scale = {
+        "i8": (127, 120, np.int8, oracle.layered_i8, 16),
+        "i16": (32767, 30000, np.int16, oracle.layered_i16, 256)}[fmt]
+    assert g + 2 * ((3 * g) >> 2) > qmax
+    dv = H.sum(0).astype(np.int64)
+    for k in (2, 3, 5):
+        r = run(H, s, np.full(2, g, dt), 16, max_iters=k, early_stop=False)
+        want = (g + dv * ((3 * qmax) >> 2)).astype(np.float32)
+        assert np.array_equal(r.Q[0] * scale, want) and np.array_equal(r.Q[1] * scale, want)
+        clamped_reading = np.float32(qmax + ((3 * qmax) >> 2))
+        assert not np.any(r.Q[0] * scale == clamped_reading)
+
+
+def _numpy_fx_layered(H, s, prior_bits, layer_size, max_iters, qmax, anum=3, ash=2, exact_q=True):
+    """Independent layered fixed-point decoder: for each check of a layer,
+    q = clamp(Q - r_old), the new r from (min1, min2) of |q| and the sign
+    parity, then Q <- (Q - r_old) + r_new in exact integers (exact_q=False:
+    Q <- q + r_new, the rejected reading).  Returns e, iterations, Q and the
+    number of check inputs that saturated."""
+    m, n = H.shape
+    rows = [np.nonzero(H[i])[0] for i in range(m)]
+    B = s.shape[0]
+    out_e = np.zeros((B, n), np.uint8)
+    out_it = np.zeros(B, np.int32)
+    out_Q = np.zeros((B, n), np.int64)
+    saturated = 0
+    for b in range(B):
+        r = [np.zeros(len(cc), np.int64) for cc in rows]
+        Q = prior_bits[b].astype(np.int64).copy()
+        for k in range(1, max_iters + 1):
+            for lo in range(0, m, layer_size):
+                for i in range(lo, lo + layer_size):
+                    cc = rows[i]
+                    x = Q[cc] - r[i]
+                    q = np.clip(x, -qmax, qmax)
+                    saturated += int(np.count_nonzero(q != x))
+                    a = np.abs(q)
+                    o = np.argsort(a, kind="stable")
+                    m1, m2 = a[o[0]], a[o[1]]
+                    neg = (q < 0).astype(np.int64)
+                    par = (int(neg.sum()) + int(s[b, i])) & 1
+                    mag = np.where(np.arange(len(cc)) == o[0], m2, m1)
+                    rn = (1 - 2 * (par ^ neg)) * ((anum * mag) >> ash)
+                    Q[cc] = (x + rn) if exact_q else (q + rn)
+                    r[i] = rn
+            e = (Q < 0).astype(np.uint8)
+            if np.array_equal((e.astype(int) @ H.T) % 2, s[b]):
+                break
+        out_e[b], out_it[b], out_Q[b] = e, k, Q
+    return out_e, out_it, out_Q, saturated
+
+
+@pytest.mark.parametrize("fmt", ["i8", "i16"])
+def test_layered_fixed_point_against_independent_decoder_saturating(fmt):
+    """Per-bit priors of large magnitude (most at or near the bound, the
+    error bits' priors pointing the wrong way half of the time), so the
+    saturation branch of the layered rule decides many check inputs."""
+    c = lp.lp_code(16)
+    H = c.hz.dense()
+    b = noise.Batch(c.hz, 31, np.arange(16), 0.06)
+    rng = np.random.default_rng(77)
+    qmax, dt, run, scale = {
+        "i8": (127, np.int8, oracle.layered_i8, 16),
+        "i16": (32767, np.int16, oracle.layered_i16, 256)}[fmt]
+    mag = rng.integers(qmax // 3, qmax + 1, size=(b.B, c.n))
+    wrong = (b.e == 1) & (rng.random((b.B, c.n)) < 0.5)
+    prior = np.where(wrong, -mag, mag).astype(dt)
+    r = run(H, b.s, prior, 16, max_iters=10)
+    e, it, Q, sat = _numpy_fx_layered(H, b.s, prior, 16, 10, qmax)
+    assert sat > 1000
+    assert np.array_equal(r.e, e) and np.array_equal(r.iters, it)
+    assert np.array_equal(r.Q * scale, Q.astype(np.float32))
+    # the rejected reading (posterior rebuilt from the saturated input) is
+    # told apart by this input
+    e2, it2, Q2, _ = _numpy_fx_layered(H, b.s, prior, 16, 10, qmax, exact_q=False)
+    assert not (np.array_equal(Q2, Q) and np.array_equal(it2, it))
