@@ -203,6 +203,7 @@ def main():
         k = int(fails.sum())
         lo, hi = gf2.wilson(k, B)
         bb["iters_host"] = it
+        bb["timed_out"] = (e_hat, conv, it, fails)     # the timed decode's outputs, before the variants
         ler[str(bb["p"])] = dict(ler=k / B, ci95=[lo, hi], converged=float(conv.mean()),
                                  mean_iters=float(it.mean()), p99_iters=float(np.percentile(it, 99)))
 
@@ -378,6 +379,7 @@ def main():
     # ---------------- CPU oracle on a bounded sample ---------------------------
     cpu = None
     cpu_detail = None
+    oracle_check = None
     if not args.no_cpu:
         import oracle
         nthr = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -386,9 +388,24 @@ def main():
         samples = [(bb["batch"].s[:S], bb["batch"].gamma[:S]) for bb in batches]
         oracle.flood_f32(H, samples[0][0][:8], samples[0][1][:8], nthreads=nthr)   # warm
         t = time.perf_counter()
-        for s_, g_ in samples:
-            oracle.flood_f32(H, s_, g_, alpha=0.75, max_iters=32, early_stop=True, nthreads=nthr)
+        orc = [oracle.flood_f32(H, s_, g_, alpha=0.75, max_iters=32, early_stop=True, nthreads=nthr)
+               for s_, g_ in samples]
         dt = time.perf_counter() - t
+        # "equal logical error rate", checked: the oracle's decisions, flags
+        # and iteration counts on the sampled shots against the timed GPU
+        # decode's, and the two failure sets
+        per_p = {}
+        mism_total = 0
+        for bb, o in zip(batches, orc):
+            e_hat, conv, it, fails = (x[:S] for x in bb["timed_out"])
+            bad = (np.any(o.e != e_hat, axis=1) | (o.converged != conv) | (o.iters != it.astype(np.int32)))
+            f_or = gf2.logical_failures(lam, bb["batch"].e[:S], o.e, o.converged)
+            mism_total += int(bad.sum())
+            per_p[str(bb["p"])] = dict(shots=int(S), mismatched_shots=int(bad.sum()),
+                                       equal_failure_sets=bool(np.array_equal(f_or, fails)),
+                                       oracle_ler=float(f_or.mean()), gpu_ler=float(fails.mean()))
+        oracle_check = dict(per_p=per_p, mismatched_shots=mism_total,
+                            compared="e, converged and iterations per shot, oracle vs the timed FP32 decode")
         cpu = dict(value=S * len(P_LIST) / dt, unit="syndromes/s", cores=int(nthr), kind="oracle",
                    sample=f"first {S} shots of each of the 3 batches (p=0.01,0.03,0.05), "
                           f"FP32 flooding, 32 iterations, early stop; {dt:.2f} s wall")
@@ -458,11 +475,15 @@ def main():
         "pcie_inclusive": pcie,
         "cpu_baseline": cpu,
         "cpu_oracle_detail": cpu_detail,
+        "oracle_check": oracle_check,
         "ler": ler,
         "variants": variants,
         "input_generation_s": gen_s,
     }
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+    if oracle_check is not None and oracle_check["mismatched_shots"] != 0:
+        print("bench.py: the GPU decode differs from the oracle on sampled shots", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -65,14 +65,25 @@ typedef struct qldpc_code_s *qldpc_code;
  * the code is CSR position e (row-major, increasing column); it indexes the
  * per-edge neural weights.
  *
- * Quasi-cyclic lift data: H is a base_m x base_n array of L x L blocks,
- * base_exp[R * base_n + C] = a >= 0 for the circulant P^a
+ * Quasi-cyclic lift data (optional): H is a base_m x base_n array of L x L
+ * blocks, base_exp[R * base_n + C] = a >= 0 for the circulant P^a
  * (P^a[r][(r + a) mod L] = 1) or -1 for a zero block; then m = base_m * L
  * and n = base_n * L, and the CSR must equal the expansion (checked).
- * The device kernels use the lift: they need the block pattern of a
- * lifted-product code LP(A, A*) with a 3 x 5 monomial base (H_Z or H_X
- * side) and L in {16, 32, 64, 128, 256, 512}; other valid matrices are accepted by
- * qldpc_code_create only if they match, else QLDPC_ERR_UNSUPPORTED. */
+ *
+ * Two device forms.  A lift with the block pattern of a lifted-product code
+ * LP(A, A*) with a 3 x 5 monomial base (H_Z or H_X side) and L in {16, 32,
+ * 64, 128, 256, 512} selects the lifted kernels, which read only the
+ * circulant shifts (every layout, both schedules).  Any other valid H --
+ * lift_L = 0, or a lift without such a pattern -- selects the edge-list
+ * decoder: flooding over the CSR (check pass) and CSC (variable pass) edge
+ * lists, one wavefront per shot with the messages in LDS, all three message
+ * formats, both prior modes, posteriors; the layered schedule, the other
+ * layouts, sessions in resident mode, mixed plans, neural min-sum and the
+ * server then return QLDPC_ERR_UNSUPPORTED.  The edge-list decoder needs
+ * max_dc * m messages (padded rows) plus the packed decisions and syndrome
+ * within 64 KB: code_create refuses codes that exceed it even in int8
+ * (QLDPC_ERR_UNSUPPORTED) and a decode in a wider format that exceeds it
+ * returns QLDPC_ERR_UNSUPPORTED. */
 typedef struct {
     int32_t m, n;
     const int32_t *row_ptr;   /* host, m + 1 entries, row_ptr[0] = 0 */
@@ -85,8 +96,9 @@ typedef struct {
 /* Validates the description, copies what the kernels need to `device`
  * (allocated once, here), and returns a new code object.  Errors:
  * INVALID_ARG (malformed CSR, lift data disagreeing with the CSR, a check of
- * degree < 2), UNSUPPORTED (no kernel for this block pattern or L),
- * OUT_OF_MEMORY, DEVICE. */
+ * degree < 2, whose check update in Algorithm 1 would have no other edge to
+ * take the minimum over), UNSUPPORTED (a code too large for the edge-list
+ * decoder), OUT_OF_MEMORY, DEVICE. */
 qldpc_status qldpc_code_create(const qldpc_code_desc *desc, int32_t device, qldpc_code *out);
 
 /* Releases the code object and its device memory.  No work using the code
@@ -210,7 +222,10 @@ qldpc_status qldpc_decode_batch_ws(qldpc_code code, const qldpc_decode_params *p
 /* Layout autotuner                                                          */
 /* ------------------------------------------------------------------------ */
 
-/* Times every kernel layout that can run `params` (wavefront per shot; one
+/* Layout tuning: the thread and block configuration and the choice between
+ * on-chip (LDS or register) and device-memory messages are the tuning space
+ * the paper lists (Table 1 and Section 3).
+ * Times every kernel layout that can run `params` (wavefront per shot; one
  * workgroup of 8 or 16 wavefronts per shot) on the caller's batch -- the
  * buffers are those of qldpc_decode_batch, decoded several times -- and
  * returns the fastest in `best` (layout and waves_per_shot filled in, other
@@ -265,7 +280,9 @@ typedef enum {
 
 /* A session owns device buffers and pinned host staging for up to
  * `max_batch` shots, a private stream, and its captured graphs.  It measures
- * what the paper's latency figure counts: host syndrome to host result. */
+ * what the paper's latency figure counts: host syndrome to host result,
+ * host-to-device and device-to-host transfers included (Section 3 and the
+ * caption of Fig. 3; the 63 us target of Section 1). */
 qldpc_status qldpc_session_create(qldpc_code code, const qldpc_decode_params *params,
                                   int32_t max_batch, int32_t io_mode, qldpc_session *out);
 qldpc_status qldpc_session_destroy(qldpc_session s);
@@ -337,6 +354,13 @@ qldpc_status qldpc_mixed_decode(qldpc_mixed plan, int32_t batch, const int32_t *
                                 const int64_t *syn_off, const int64_t *err_off, const uint32_t *syndromes,
                                 const float *priors, uint32_t *errors, uint8_t *converged,
                                 uint8_t *iters_used, void *stream);
+
+/* Sets the persistent grid sizes of a plan: `reg_waves` wavefronts for each
+ * (pattern, lift) with L <= 64 and `block_workgroups` workgroups for L = 128
+ * (0 keeps the current value; defaults 12 and 2 per compute unit).  With
+ * fewer waves than tiles every wavefront claims several tiles in turn.  The
+ * plan's captured graphs are dropped.  Errors: INVALID_ARG. */
+qldpc_status qldpc_mixed_set_grid(qldpc_mixed plan, int32_t reg_waves, int32_t block_workgroups);
 
 /* Times the register-resident persistent grid (codes with L <= 64) at 6,
  * 12, 24 and 48 wavefronts per compute unit on the caller's batch, keeps
@@ -484,11 +508,13 @@ qldpc_status qldpc_server_loadgen(qldpc_server srv, const qldpc_loadgen_config *
                                   qldpc_loadgen_result *result, double *lat_us, int64_t lat_cap);
 
 /* Host helper: int8 Q4 prior clamp(round-half-away-from-zero(16 * llr),
- * -127, 127) for `count` values (host arrays). */
+ * -127, 127) for `count` values (host arrays): the quantisation of the
+ * 8-bit integer format (Table 1, reduced-precision data types; Section 3). */
 qldpc_status qldpc_quantize_prior(const float *llr, int8_t *out, int64_t count);
 
 /* Host helper: int16 Q8 prior clamp(round-half-away-from-zero(256 * llr),
- * -32767, 32767) for `count` values (host arrays). */
+ * -32767, 32767) for `count` values (host arrays): the quantisation of the
+ * 16-bit integer format (Table 1; Section 3). */
 qldpc_status qldpc_quantize_prior_q8(const float *llr, int16_t *out, int64_t count);
 
 #ifdef __cplusplus

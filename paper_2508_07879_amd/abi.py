@@ -114,6 +114,7 @@ def _load():
         "qldpc_mixed_create": ([C.POINTER(vp), i32, C.POINTER(qldpc_decode_params), i32, i32, C.POINTER(vp)], i32),
         "qldpc_mixed_destroy": ([vp], i32),
         "qldpc_mixed_decode": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+        "qldpc_mixed_set_grid": ([vp, i32, i32], i32),
         "qldpc_mixed_autotune": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32)], i32),
         "qldpc_server_create": ([C.POINTER(qldpc_server_config), C.POINTER(vp)], i32),
         "qldpc_server_info": ([vp, vp, vp, vp, vp], i32),
@@ -339,6 +340,10 @@ def qldpc_mixed_decode(x, batch: int, shot_code, syn_off, err_off, syndromes, pr
                                   _ptr(priors), _ptr(errors), _ptr(converged), _ptr(iters_used), _stream(stream)))
 
 
+def qldpc_mixed_set_grid(x, reg_waves: int = 0, block_workgroups: int = 0) -> None:
+    _check(lib.qldpc_mixed_set_grid(x, int(reg_waves), int(block_workgroups)))
+
+
 def qldpc_mixed_autotune(x, batch: int, shot_code, syn_off, err_off, syndromes, priors, errors, converged,
                          iters_used=None, stream=None) -> int:
     w = C.c_int32()
@@ -384,13 +389,19 @@ def qldpc_server_submit(srv, code_id: int, decoder: int, nshots: int, host_syn, 
                                    _np(host_err), _np(host_conv), _np(host_iters), C.c_uint64(req_id)))
 
 
-def qldpc_server_poll(srv, max_n: int = 1024):
+def qldpc_server_poll(srv, max_n: int = 1024, raise_errors: bool = True):
+    """Completions, oldest first.  A failed server reports its status after
+    handing out the completions it holds: raise_errors=False returns
+    (completions, status) instead of raising."""
     buf = (qldpc_completion * max_n)()
     n = C.c_int32()
     st = lib.qldpc_server_poll(srv, buf, int(max_n), C.byref(n))
+    out = [buf[i] for i in range(n.value)]
+    if not raise_errors:
+        return out, st
     if st not in (QLDPC_OK, QLDPC_ERR_NOT_READY):
         _check(st)
-    return [buf[i] for i in range(n.value)]
+    return out
 
 
 def qldpc_server_destroy(srv) -> None:

@@ -1,7 +1,9 @@
 // Host runtime of the decoder library: C ABI, code objects, validation and
-// kernel selection.  The Tanner graph of a code object is described by its
-// quasi-cyclic lift (Section 2: H and its sets S_v(m), S_c(n)); the kernels
-// need only the circulant shifts of each block, uploaded once at creation.
+// kernel selection.  A code object holds the Tanner graph of H (Section 2:
+// the sets S_v(m), S_c(n)) in one of two device forms, uploaded once at
+// creation: for a lifted-product code with a compiled block pattern only the
+// circulant shifts of its blocks; for any other H its edge lists (CSR for
+// the check pass, CSC positions for the variable pass).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -82,6 +84,22 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     key->fmt = p->fmt;
     key->sched = p->sched;
     key->per_bit = p->prior_mode == QLDPC_PRIOR_PER_BIT;
+    if (code->L == 0) {
+        // edge-list decoder: flooding, one wavefront per shot, messages in LDS
+        a->code = nullptr;
+        if (p->sched != QLDPC_FLOOD)
+            return fail(QLDPC_ERR_UNSUPPORTED, "decode: the layered schedule needs quasi-cyclic lift data");
+        if (p->layout != QLDPC_LAYOUT_AUTO && p->layout != QLDPC_LAYOUT_WAVE)
+            return fail(QLDPC_ERR_UNSUPPORTED, "decode: a code without a compiled block pattern has one layout "
+                                               "(wavefront per shot)");
+        const int b = p->fmt == QLDPC_F32 ? 4 : p->fmt == QLDPC_I16Q8 ? 2 : 1;
+        if (gen_lds_bytes(code->m, code->n, code->max_dc, b) > kGenMaxLds)
+            return fail(QLDPC_ERR_UNSUPPORTED, "decode: the edge messages of this code do not fit one wavefront's "
+                                               "LDS in this format");
+        key->layout = QLDPC_LAYOUT_WAVE;
+        key->nw = 0;
+        return QLDPC_OK;
+    }
     const bool block_ok = p->sched == QLDPC_FLOOD && code->L >= 64;
     int layout = p->layout, nw = p->waves_per_shot;
     if (layout == QLDPC_LAYOUT_AUTO && code->L > 128) layout = QLDPC_LAYOUT_HBM;   // messages do not fit on chip
@@ -127,6 +145,85 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     key->layout = layout;
     key->nw = nw;
     return QLDPC_OK;
+}
+
+}  // namespace qldpc
+
+namespace {
+
+// A code object over the edge lists of a validated CSR: row_ptr, col_idx,
+// and for each variable its edges in increasing check order as LDS slots
+// j * m + r of the edge-list decoder.  Refused (UNSUPPORTED) when its
+// messages would not fit one wavefront's LDS even in int8.
+qldpc_status create_generic(const qldpc_code_desc *d, int32_t max_dc, int32_t max_dv, int32_t device,
+                            qldpc_code *out) {
+    const int32_t m = d->m, n = d->n, nnz = d->row_ptr[d->m];
+    if (gen_lds_bytes(m, n, max_dc, 1) > kGenMaxLds)
+        return fail(QLDPC_ERR_UNSUPPORTED, "code_create: code too large for the edge-list decoder (messages of "
+                                           "max check degree x checks must fit 64 KB of LDS in int8)");
+    std::vector<int32_t> col_ptr(n + 1, 0), vn_slot(nnz);
+    for (int32_t f = 0; f < nnz; ++f) col_ptr[d->col_idx[f] + 1]++;
+    for (int32_t c = 0; c < n; ++c) col_ptr[c + 1] += col_ptr[c];
+    std::vector<int32_t> fill(col_ptr.begin(), col_ptr.end() - 1);
+    for (int32_t r = 0; r < m; ++r)   // rows in increasing order: each column's list is sorted by row
+        for (int32_t f = d->row_ptr[r]; f < d->row_ptr[r + 1]; ++f)
+            vn_slot[fill[d->col_idx[f]]++] = (f - d->row_ptr[r]) * m + r;
+    auto *code = new (std::nothrow) qldpc_code_s();
+    if (!code) return fail(QLDPC_ERR_OUT_OF_MEMORY, "code_create: host allocation failed");
+    code->m = m;
+    code->n = n;
+    code->nnz = nnz;
+    code->max_dc = max_dc;
+    code->max_dv = max_dv;
+    code->L = 0;
+    code->which = -1;
+    code->device = device;
+    const size_t words = (size_t)(m + 1) + nnz + (n + 1) + nnz;
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) { delete code; return hip_fail(e, "hipGetDevice"); }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) { delete code; return hip_fail(e, "hipSetDevice"); }
+    e = hipMalloc(&code->gen_mem, words * sizeof(int32_t));
+    if (e != hipSuccess) {
+        (void)hipSetDevice(prev);
+        delete code;
+        return fail(QLDPC_ERR_OUT_OF_MEMORY, "code_create: hipMalloc failed");
+    }
+    int32_t *base = static_cast<int32_t *>(code->gen_mem);
+    GenCode &g = code->gen;
+    g.m = m;
+    g.n = n;
+    g.nnz = nnz;
+    g.max_dc = max_dc;
+    g.row_ptr = base;
+    g.col_idx = base + (m + 1);
+    g.col_ptr = base + (m + 1) + nnz;
+    g.vn_slot = base + (m + 1) + nnz + (n + 1);
+    std::vector<int32_t> host;
+    host.reserve(words);
+    host.insert(host.end(), d->row_ptr, d->row_ptr + m + 1);
+    host.insert(host.end(), d->col_idx, d->col_idx + nnz);
+    host.insert(host.end(), col_ptr.begin(), col_ptr.end());
+    host.insert(host.end(), vn_slot.begin(), vn_slot.end());
+    e = hipMemcpy(code->gen_mem, host.data(), words * sizeof(int32_t), hipMemcpyHostToDevice);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        (void)hipFree(code->gen_mem);
+        delete code;
+        return hip_fail(e, "code_create: upload");
+    }
+    *out = code;
+    return QLDPC_OK;
+}
+
+}  // namespace
+
+namespace qldpc {
+
+hipError_t launch_code_decode(qldpc_code code, const LaunchKey &k, const DecodeArgs &a, hipStream_t stream) {
+    if (code->L == 0) return launch_generic_decode(code->gen, k, a, stream);
+    return launch_decode(k, a, stream);
 }
 
 }  // namespace qldpc
@@ -200,8 +297,7 @@ qldpc_status qldpc_code_create(const qldpc_code_desc *d, int32_t device, qldpc_c
     int32_t max_dv = 0;
     for (int32_t c = 0; c < d->n; ++c) max_dv = std::max(max_dv, coldeg[c]);
 
-    if (d->lift_L <= 0 || !d->base_exp)
-        return fail(QLDPC_ERR_UNSUPPORTED, "code_create: the device kernels need quasi-cyclic lift data");
+    if (d->lift_L <= 0 || !d->base_exp) return create_generic(d, max_dc, max_dv, device, out);
     const int32_t L = d->lift_L, bm = d->base_m, bn = d->base_n;
     if (bm <= 0 || bn <= 0 || (int64_t)bm * L != d->m || (int64_t)bn * L != d->n)
         return fail(QLDPC_ERR_INVALID_ARG, "code_create: lift dimensions disagree with m, n");
@@ -235,11 +331,9 @@ qldpc_status qldpc_code_create(const qldpc_code_desc *d, int32_t device, qldpc_c
             if (ok) which = w;
         }
     }
-    if (which < 0)
-        return fail(QLDPC_ERR_UNSUPPORTED,
-                    "code_create: block pattern is not a 3x5 lifted-product H_Z or H_X pattern");
-    if (L != 16 && L != 32 && L != 64 && L != 128 && L != 256 && L != 512)
-        return fail(QLDPC_ERR_UNSUPPORTED, "code_create: lift size must be 16, 32, 64, 128, 256 or 512");
+    // a valid lift without a compiled block pattern or lift size: edge lists
+    if (which < 0 || (L != 16 && L != 32 && L != 64 && L != 128 && L != 256 && L != 512))
+        return create_generic(d, max_dc, max_dv, device, out);
 
     auto *code = new (std::nothrow) qldpc_code_s();
     if (!code) return fail(QLDPC_ERR_OUT_OF_MEMORY, "code_create: host allocation failed");
@@ -289,6 +383,7 @@ qldpc_status qldpc_code_create(const qldpc_code_desc *d, int32_t device, qldpc_c
 qldpc_status qldpc_code_destroy(qldpc_code code) {
     if (!code) return QLDPC_OK;
     if (code->dev) (void)hipFree(code->dev);
+    if (code->gen_mem) (void)hipFree(code->gen_mem);
     delete code;
     return QLDPC_OK;
 }
@@ -338,7 +433,7 @@ qldpc_status decode_impl(qldpc_code code, const qldpc_decode_params *p, int32_t 
     a.post = post;
     k.post = post != nullptr;
     const hipError_t e = k.layout == QLDPC_LAYOUT_HBM ? launch_hbm_decode(k, a, ws, (hipStream_t)stream)
-                                                      : launch_decode(k, a, (hipStream_t)stream);
+                                                      : launch_code_decode(code, k, a, (hipStream_t)stream);
     if (e == hipErrorNotSupported)
         return fail(QLDPC_ERR_UNSUPPORTED, std::string(who) + ": no kernel for this format/schedule/layout/L");
     if (e != hipSuccess) return hip_fail(e, "decode launch");
@@ -381,7 +476,7 @@ qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, 
     if (code->L > 128) return fail(QLDPC_ERR_UNSUPPORTED, "autotune: lifts above 128 have one layout (HBM messages)");
     struct Cand { int layout, nw; };
     std::vector<Cand> cands = {{QLDPC_LAYOUT_WAVE, 0}};
-    if (code->L <= 64) cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});
+    if (code->L > 0 && code->L <= 64) cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});
     if (params->sched == QLDPC_FLOOD && code->L >= 64) {
         cands.push_back({QLDPC_LAYOUT_BLOCK, 8});
         cands.push_back({QLDPC_LAYOUT_BLOCK, 16});
@@ -469,7 +564,7 @@ qldpc_status qldpc_tune_load(qldpc_code code, const char *path) {
             while (in >> v) nums.push_back(v);
         }
     }
-    if (L < 0 || pattern < 0 || nums.size() % 4 != 0) return fail(QLDPC_ERR_INVALID_ARG, "tune_load: malformed file");
+    if (L < 0 || pattern < -1 || nums.size() % 4 != 0) return fail(QLDPC_ERR_INVALID_ARG, "tune_load: malformed file");
     if (L != code->L || pattern != code->which) return QLDPC_OK;   // for another code
     std::lock_guard<std::mutex> g(code->tune_mu);
     for (size_t i = 0; i < nums.size(); i += 4) {

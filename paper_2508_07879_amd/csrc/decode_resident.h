@@ -2,9 +2,11 @@
 // between requests, so that a request costs neither a kernel launch nor a
 // stream synchronisation.
 //
-// The grid has one workgroup per shot slot.  Thread 0 of workgroup 0 polls
-// the doorbell page in mapped host memory; on a new sequence number it relays
-// [sequence, batch] to the other workgroups through a device-memory mailbox.
+// The grid has one workgroup per shot slot.  The whole of wave 0 of
+// workgroup 0 polls the doorbell page in mapped host memory (every lane
+// loads, so the poll loop and its exit are wave-uniform); on a new sequence
+// number it relays [sequence, batch] to the other workgroups through a
+// device-memory mailbox.
 // Workgroup w < batch decodes shot w from the mapped staging buffers (inputs
 // written by the host before it rang), makes its results visible to the
 // host, then publishes the sequence number in done_seq[w].

@@ -286,7 +286,9 @@ __device__ __forceinline__ int bperm(int addr, int v) { return __builtin_amdgcn_
 // `lds` points to WaveLds<...>::bytes of this wave's LDS.
 // ---------------------------------------------------------------------------
 // Check rule with per-edge scales (neural min-sum): r_j = sgn_j * fl(w_j *
-// excluded_min_j).
+// excluded_min_j).  A weight may be negative: the product then carries its
+// own sign bit, and the check sign flips it (XOR), as multiplying by sgn_j
+// would.
 namespace wave {
 template <int DC>
 __device__ __forceinline__ void cn_f32_weighted(float (&v)[DC], uint32_t P, const float (&wj)[DC]) {
@@ -301,8 +303,8 @@ __device__ __forceinline__ void cn_f32_weighted(float (&v)[DC], uint32_t P, cons
     for (int j = 0; j < DC; ++j) P ^= fbits(v[j]);
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
-        const float mag = wj[j] * ((fabsf(v[j]) == m1) ? m2 : m1);
-        v[j] = ubits(fbits(mag) | ((P ^ fbits(v[j])) & 0x80000000u));
+        const float wm = wj[j] * ((fabsf(v[j]) == m1) ? m2 : m1);
+        v[j] = ubits(fbits(wm) ^ ((P ^ fbits(v[j])) & 0x80000000u));
     }
 }
 

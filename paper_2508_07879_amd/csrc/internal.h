@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/qldpc.h"
+#include "decode_generic_api.h"
 #include "kernels.h"
 
 namespace qldpc {
@@ -39,8 +40,10 @@ qldpc_status hip_error(hipError_t e, const char *what);
 
 struct qldpc_code_s {
     int32_t m = 0, n = 0, nnz = 0, max_dc = 0, max_dv = 0;
-    int32_t L = 0, which = -1, device = 0;
-    qldpc::DevCode *dev = nullptr;   // device copy of the shift tables
+    int32_t L = 0, which = -1, device = 0;   // L = 0: no compiled block pattern (edge-list kernel)
+    qldpc::DevCode *dev = nullptr;   // device copy of the shift tables (lifted codes)
+    qldpc::GenCode gen{};            // device edge lists (codes without a compiled pattern)
+    void *gen_mem = nullptr;         // the one allocation behind `gen`
     std::mutex tune_mu;
     std::map<int, qldpc::TuneChoice> tune;
 };
@@ -51,5 +54,10 @@ namespace qldpc {
 // arguments for a decode of `batch` shots (buffers set by the caller).
 qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32_t batch, LaunchKey *key,
                             DecodeArgs *args);
+
+// Launches the on-chip decoder that prepare_decode chose for `code`: the
+// edge-list kernel for codes without a compiled block pattern, else the
+// lifted kernels (launch_decode).
+hipError_t launch_code_decode(qldpc_code code, const LaunchKey &k, const DecodeArgs &a, hipStream_t stream);
 
 }  // namespace qldpc

@@ -188,6 +188,17 @@ qldpc_status qldpc_mixed_decode(qldpc_mixed x, int32_t batch, const int32_t *sho
     return QLDPC_OK;
 }
 
+qldpc_status qldpc_mixed_set_grid(qldpc_mixed x, int32_t reg_waves, int32_t block_workgroups) {
+    if (!x || reg_waves < 0 || block_workgroups < 0)
+        return set_error(QLDPC_ERR_INVALID_ARG, "mixed_set_grid: bad arguments");
+    std::lock_guard<std::mutex> g(x->mu);
+    if (reg_waves > 0) x->waves = reg_waves;
+    if (block_workgroups > 0) x->waves128 = block_workgroups;
+    for (auto &kv : x->graphs) (void)hipGraphExecDestroy(kv.second);
+    x->graphs.clear();
+    return QLDPC_OK;
+}
+
 qldpc_status qldpc_mixed_autotune(qldpc_mixed x, int32_t batch, const int32_t *shot_code, const int64_t *syn_off,
                                   const int64_t *err_off, const uint32_t *syn, const float *prior, uint32_t *err,
                                   uint8_t *conv, uint8_t *iters, void *stream, int32_t *best_waves) {

@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -83,6 +84,11 @@ struct qldpc_server_s {
     std::string worker_error;
     std::thread worker;
     size_t slot_bytes = 0;
+    // Failure injection for tests of the error path: the launch of this
+    // micro-batch (1-based count) fails before anything is enqueued
+    // (environment variable QLDPC_TEST_FAIL_LAUNCH at create time; 0 = never).
+    int64_t fail_launch_at = 0;
+    int64_t launches = 0;
 };
 
 namespace {
@@ -112,6 +118,8 @@ size_t slot_device_bytes(int64_t shots, int32_t sw, int32_t ew) {
 
 // Packs the slot's requests into its staging and launches the micro-batch.
 qldpc_status launch_slot(qldpc_server srv, Slot &s) {
+    if (++srv->launches == srv->fail_launch_at)
+        return set_error(QLDPC_ERR_DEVICE, "server: injected launch failure");
     const int32_t nc = (int32_t)srv->codes.size();
     // plain min-sum shots first (ragged, any code), then neural shots per code
     int32_t shot = 0;
@@ -181,35 +189,58 @@ qldpc_status launch_slot(qldpc_server srv, Slot &s) {
     return QLDPC_OK;
 }
 
-// Scatters a finished slot's results and posts completions.
-void finish_slot(qldpc_server srv, Slot &s) {
+qldpc_completion completion_of(const Request &r, qldpc_status status, int64_t t) {
+    qldpc_completion q{};
+    q.req_id = r.id;
+    q.code_id = r.code;
+    q.decoder = r.decoder;
+    q.nshots = r.nshots;
+    q.status = status;
+    q.t_submit_ns = r.t_submit;
+    q.t_done_ns = t;
+    return q;
+}
+
+// Retires a slot: on success scatters its results into the requests' host
+// buffers; on failure leaves those buffers untouched.  Either way every
+// request of the slot gets one completion carrying `status`.
+void finish_slot(qldpc_server srv, Slot &s, qldpc_status status) {
     const int64_t t = now_ns();
     std::vector<qldpc_completion> done;
     done.reserve(s.reqs.size());
     for (const Request &r : s.reqs) {
-        const qldpc_code c = srv->codes[r.code];
-        const int32_t ew = (c->n + 31) / 32;
-        for (int32_t i = 0; i < r.nshots; ++i) {
-            const int32_t sh = r.first_shot + i;
-            if (r.err) std::memcpy(r.err + (size_t)i * ew, s.h_err + s.h_eoff[sh], sizeof(uint32_t) * ew);
-            if (r.conv) r.conv[i] = s.h_conv[sh];
-            if (r.iters) r.iters[i] = s.h_iters[sh];
+        if (status == QLDPC_OK) {
+            const qldpc_code c = srv->codes[r.code];
+            const int32_t ew = (c->n + 31) / 32;
+            for (int32_t i = 0; i < r.nshots; ++i) {
+                const int32_t sh = r.first_shot + i;
+                if (r.err) std::memcpy(r.err + (size_t)i * ew, s.h_err + s.h_eoff[sh], sizeof(uint32_t) * ew);
+                if (r.conv) r.conv[i] = s.h_conv[sh];
+                if (r.iters) r.iters[i] = s.h_iters[sh];
+            }
         }
-        qldpc_completion q{};
-        q.req_id = r.id;
-        q.code_id = r.code;
-        q.decoder = r.decoder;
-        q.nshots = r.nshots;
-        q.status = QLDPC_OK;
-        q.t_submit_ns = r.t_submit;
-        q.t_done_ns = t;
-        done.push_back(q);
+        done.push_back(completion_of(r, status, t));
     }
     srv->inflight_shots -= s.shots;
     s.reqs.clear();
+    s.shots = 0;
     s.busy = false;
     std::lock_guard<std::mutex> g(srv->mu);
     srv->completions.insert(srv->completions.end(), done.begin(), done.end());
+}
+
+// Records the first failure; the server then stops admitting, and the
+// requests still queued complete with that status.
+void fail_server(qldpc_server srv, qldpc_status st, const std::string &msg) {
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (srv->worker_status == QLDPC_OK) {
+        srv->worker_status = st;
+        srv->worker_error = msg;
+    }
+    srv->stop = true;
+    const int64_t t = now_ns();
+    for (const Request &r : srv->pending) srv->completions.push_back(completion_of(r, srv->worker_status, t));
+    srv->pending.clear();
 }
 
 void worker_loop(qldpc_server srv) {
@@ -222,17 +253,18 @@ void worker_loop(qldpc_server srv) {
             if (!s.busy) continue;
             hipError_t q = hipEventQuery(s.done);
             if (q == hipSuccess) {
-                finish_slot(srv, s);
+                finish_slot(srv, s, QLDPC_OK);
                 progressed = true;
             } else if (q != hipErrorNotReady) {
-                std::lock_guard<std::mutex> g(srv->mu);
-                srv->worker_status = QLDPC_ERR_DEVICE;
-                srv->worker_error = std::string("server: ") + hipGetErrorString(q);
-                srv->stop = true;
+                fail_server(srv, QLDPC_ERR_DEVICE, std::string("server: ") + hipGetErrorString(q));
+                (void)hipStreamSynchronize(s.stream);
+                finish_slot(srv, s, QLDPC_ERR_DEVICE);
+                progressed = true;
             }
         }
         // admit queued requests into free slots
         for (Slot &s : srv->slots) {
+            if (srv->stop) break;
             if (s.busy) continue;
             {
                 std::lock_guard<std::mutex> g(srv->mu);
@@ -250,10 +282,11 @@ void worker_loop(qldpc_server srv) {
             srv->inflight_shots += n;
             qldpc_status rc = launch_slot(srv, s);
             if (rc != QLDPC_OK) {
-                std::lock_guard<std::mutex> g(srv->mu);
-                srv->worker_status = rc;
-                srv->worker_error = qldpc_last_error();
-                srv->stop = true;
+                // the micro-batch may be partly enqueued: wait for what was,
+                // then fail its requests without touching their buffers
+                fail_server(srv, rc, qldpc_last_error());
+                (void)hipStreamSynchronize(s.stream);
+                finish_slot(srv, s, rc);
             }
             progressed = true;
         }
@@ -261,11 +294,12 @@ void worker_loop(qldpc_server srv) {
         for (Slot &s : srv->slots) any_busy = any_busy || s.busy;
         if (srv->stop && !any_busy) break;
         if (srv->stop && any_busy) {
-            // drain: wait for the device, then retire
+            // drain: every busy slot was launched completely (its event is
+            // recorded); wait for its stream, then retire
             for (Slot &s : srv->slots)
                 if (s.busy) {
-                    (void)hipEventSynchronize(s.done);
-                    finish_slot(srv, s);
+                    const hipError_t q = hipStreamSynchronize(s.stream);
+                    finish_slot(srv, s, q == hipSuccess ? QLDPC_OK : QLDPC_ERR_DEVICE);
                 }
             break;
         }
@@ -292,12 +326,15 @@ qldpc_status qldpc_server_create(const qldpc_server_config *cfg, qldpc_server *o
         return set_error(QLDPC_ERR_INVALID_ARG, "server_create: nms_T must be in [1, 255]");
     for (int c = 0; c < cfg->ncodes; ++c) {
         if (!cfg->codes[c]) return set_error(QLDPC_ERR_INVALID_ARG, "server_create: null code");
-        if (cfg->nms_weights && cfg->nms_weights[c] && cfg->codes[c]->which != 0)
-            return set_error(QLDPC_ERR_UNSUPPORTED, "server_create: neural weights for H_Z-pattern codes only");
+        const int L = cfg->codes[c]->L;
+        if (cfg->nms_weights && cfg->nms_weights[c] && (cfg->codes[c]->which != 0 || (L != 32 && L != 64 && L != 128)))
+            return set_error(QLDPC_ERR_UNSUPPORTED,
+                             "server_create: neural weights for H_Z-pattern codes with L = 32, 64 or 128 only");
     }
     auto *srv = new (std::nothrow) qldpc_server_s();
     if (!srv) return set_error(QLDPC_ERR_OUT_OF_MEMORY, "server_create: host allocation");
     srv->cfg = *cfg;
+    if (const char *f = std::getenv("QLDPC_TEST_FAIL_LAUNCH")) srv->fail_launch_at = std::atoll(f);
     srv->codes.assign(cfg->codes, cfg->codes + cfg->ncodes);
     srv->weights.assign(cfg->ncodes, nullptr);
     for (int c = 0; c < cfg->ncodes; ++c) {

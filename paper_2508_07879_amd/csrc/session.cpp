@@ -123,7 +123,7 @@ qldpc_status enqueue(qldpc_session s, int32_t batch) {
     }
     a.post = nullptr;
     k.post = 0;
-    hipError_t e = launch_decode(k, a, s->stream);
+    hipError_t e = launch_code_decode(s->code, k, a, s->stream);
     if (e == hipErrorNotSupported) return set_error(QLDPC_ERR_UNSUPPORTED, "session: no kernel for these parameters");
     if (e != hipSuccess) return hip_error(e, "session: launch");
     return QLDPC_OK;

@@ -80,20 +80,30 @@ def test_code_create_rejects_malformed_input(case):
     assert ei.value.status == abi.QLDPC_ERR_INVALID_ARG
 
 
-def test_code_create_rejects_unsupported_patterns():
+def test_code_create_takes_any_valid_matrix_and_refuses_oversized_ones():
+    """A valid H without a compiled block pattern, or without lift data at
+    all, goes to the edge-list decoder: on a machine without a GPU, creation
+    then fails only at the device step.  A code whose messages cannot fit one
+    wavefront's LDS even in int8 is refused before any device call."""
     from paper_2508_07879_amd import abi
     from workload import lp
-    # a valid quasi-cyclic matrix whose block pattern has no compiled kernel
     base = -np.ones((2, 4), np.int64)
     base[0, :3] = [0, 1, 2]
     base[1, 1:] = [3, 0, 1]
     rp, ci = lp.expand_csr(base, 16)
+    for lift, b in ((16, base), (0, None)):
+        try:
+            h = abi.qldpc_code_create(32, 64, rp, ci, lift, b)
+            abi.qldpc_code_destroy(h)
+        except abi.QldpcError as e:
+            assert e.status == abi.QLDPC_ERR_DEVICE, str(e)
+    # 40000 checks of degree 2 on a ring: 80000 int8 messages > 64 KB
+    m = 40000
+    rp = np.arange(0, 2 * m + 1, 2, dtype=np.int32)
+    ci = np.stack([np.arange(m), (np.arange(m) + 1) % m], 1)
+    ci.sort(axis=1)
     with pytest.raises(abi.QldpcError) as ei:
-        abi.qldpc_code_create(32, 64, rp, ci, 16, base)
-    assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED
-    # no lift data at all
-    with pytest.raises(abi.QldpcError) as ei:
-        abi.qldpc_code_create(32, 64, rp, ci, 0, None)
+        abi.qldpc_code_create(m, m, rp, ci.reshape(-1).astype(np.int32), 0, None)
     assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED
 
 

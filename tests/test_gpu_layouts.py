@@ -98,7 +98,7 @@ def test_autotune_records_a_valid_choice_and_roundtrips():
     err, conv, it, _ = dec.outputs(256)
     p = dec.params()
     best = abi.qldpc_autotune(dec.handle, p, 256, syn, pr, err, conv, it)
-    assert best.layout in (abi.QLDPC_LAYOUT_WAVE, abi.QLDPC_LAYOUT_BLOCK)
+    assert best.layout in (abi.QLDPC_LAYOUT_WAVE, abi.QLDPC_LAYOUT_BLOCK, abi.QLDPC_LAYOUT_WAVE_REG)
     assert best.waves_per_shot in (0, 8, 16)
     g = gpu_decode(dec, b.s, b.gamma, layout=0)    # AUTO now uses the recorded choice
     o = oracle_decode(H, b.s, b.gamma)

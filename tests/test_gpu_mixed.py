@@ -1,7 +1,9 @@
 """Mixed-code persistent decoding against the CPU oracle and against
 single-code decoding of the same shots (bit-identical: a shot's result does
 not depend on its batch mates), eager and through the captured hipGraph
-(replayed several times with other device work in between)."""
+(replayed several times with other device work in between).  The persistent
+path proper -- every wavefront and workgroup claiming many tiles in turn --
+is checked on small grids and at the benchmark's full 262144-shot size."""
 import numpy as np
 import pytest
 
@@ -31,10 +33,12 @@ def setup():
     return _state
 
 
-def run_mixed(st, mb, use_graph, reps=1, between=None):
+def run_mixed(st, mb, use_graph, reps=1, between=None, grid=None):
     prm = st["decs"][0].params(max_iters=32)
     plan = abi.qldpc_mixed_create([d.handle for d in st["decs"]], prm, mb.B, use_graph)
     try:
+        if grid is not None:
+            abi.qldpc_mixed_set_grid(plan, *grid)
         dev = dict(cid=to_dev(mb.cid.astype(np.int32)), so=to_dev(mb.syn_off), eo=to_dev(mb.err_off),
                    syn=to_dev(mb.syn.view(np.int32)), pr=to_dev(mb.gamma))
         outs = []
@@ -148,3 +152,64 @@ def test_mixed_autotune_and_bad_code_ids():
         assert np.all(c[:10] == 7) and np.all(c[10:] <= 1)
     finally:
         abi.qldpc_mixed_destroy(plan)
+
+
+def single_code_all(st, mb, out):
+    """Every shot of the mixed result equals its single-code decode."""
+    split = mb.split_errors(out[0].view(np.uint32))
+    for c in range(len(LS)):
+        idx, _ = mb.e[c]
+        if idx.size == 0:
+            continue
+        g = gpu_decode(st["decs"][c], mb.s[c], mb.gamma[idx], posterior=False)
+        assert np.array_equal(g[0], split[c]), f"L={LS[c]}: decisions differ from the single-code decode"
+        assert np.array_equal(g[1], out[1][idx]) and np.array_equal(g[2], out[2][idx].astype(np.int32))
+    return split
+
+
+def oracle_sample(st, mb, out, split, per_code=24):
+    """The first and last shots of each code by index and its unconverged
+    shots, up to per_code of each, against the oracle."""
+    for c in range(len(LS)):
+        idx, _ = mb.e[c]
+        if idx.size == 0:
+            continue
+        k = idx.size
+        unconv = np.nonzero(out[1][idx] == 0)[0][:per_code]
+        pick = np.unique(np.concatenate([np.arange(min(per_code, k)), np.arange(max(0, k - per_code), k), unconv]))
+        o = oracle.flood_f32(st["H"][c], mb.s[c][pick], mb.gamma[idx[pick]], max_iters=32)
+        assert np.array_equal(split[c][pick], o.e), f"L={LS[c]}: sampled decisions differ from the oracle"
+        assert np.array_equal(out[1][idx[pick]], o.converged)
+        assert np.array_equal(out[2][idx[pick]].astype(np.int32), o.iters)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_persistent_grids_claim_many_tiles(use_graph):
+    """37 register wavefronts per lift and 11 workgroups for L = 128 over
+    6000 shots: every wavefront and workgroup decodes many tiles in turn."""
+    st = setup()
+    mb = MixedBatch(st["codes"], 55, 6000)
+    reg_waves, block_wgs = 37, 11
+    for c, L in enumerate(LS):
+        n = int((mb.cid == c).sum())
+        tiles = -(-n // (64 // L)) if L <= 64 else n
+        assert tiles >= 4 * (reg_waves if L <= 64 else block_wgs), (L, n)
+    (out,) = run_mixed(st, mb, use_graph, grid=(reg_waves, block_wgs))
+    split = single_code_all(st, mb, out)
+    oracle_sample(st, mb, out, split)
+
+
+def test_full_size_mixed_batch():
+    """The benchmark's 262144-shot mixed batch at the default grid sizes
+    (3072 register wavefronts per lift, 512 workgroups for L = 128, so tiles
+    outnumber waves for every lift): every shot against its single-code
+    decode, a sample against the oracle."""
+    st = setup()
+    mb = MixedBatch(st["codes"], 20250807 + 99, 262144)
+    for c, L in enumerate(LS):
+        n = int((mb.cid == c).sum())
+        tiles = -(-n // (64 // L)) if L <= 64 else n
+        assert tiles > (3072 if L <= 64 else 512), (L, n)
+    (out,) = run_mixed(st, mb, True)
+    split = single_code_all(st, mb, out)
+    oracle_sample(st, mb, out, split, per_code=16)

@@ -2,8 +2,9 @@
 
 * Forward: every iteration's posterior equals the oracle's FP32 flooding
   with the same per-edge weights (within 1e-5 relative; the order of
-  operations is the same, so in practice bit-exact); weights all alpha give
-  plain min-sum.
+  operations is the same, so in practice bit-exact), for positive weights and
+  for weights of mixed sign (a negative weight flips its edge's message);
+  weights all alpha give plain min-sum.
 * Backward: the FP32 adjoint kernel matches the oracle's FP64 adjoint,
   evaluated on the oracle's own FP32 forward trajectory, to 1e-4 of the sum
   of absolute per-shot terms of each weight's gradient; two runs give
@@ -39,6 +40,17 @@ def code(L):
     return _codes[L]
 
 
+def weights(seed, T, nnz, lo, hi, neg_frac=0.0):
+    """U(lo, hi) weights with a random fraction of entries negated."""
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(lo, hi, size=(T, nnz)).astype(np.float32)
+    if neg_frac:
+        flip = rng.random(w.shape) < neg_frac
+        w[flip] = -w[flip]
+        assert flip.any()
+    return w
+
+
 def forward(dec, b, w):
     T = w.shape[0]
     syn = to_dev(bits.pack_bits(b.s).view(np.int32))
@@ -51,12 +63,14 @@ def forward(dec, b, w):
     return syn, wt, ws, post
 
 
+@pytest.mark.parametrize("wlo", [0.4, -0.6])
 @pytest.mark.parametrize("L", [32, 64, 128])
-def test_forward_matches_oracle(L):
+def test_forward_matches_oracle(L, wlo):
     c, H, dec = code(L)
     b = noise.Batch(c.hz, 41, np.arange(37), 0.05)
     T = 6
-    w = np.random.default_rng(L).uniform(0.4, 1.0, size=(T, c.hz.nnz)).astype(np.float32)
+    w = np.random.default_rng(L).uniform(wlo, 1.0, size=(T, c.hz.nnz)).astype(np.float32)
+    assert (w < 0).any() == (wlo < 0)
     _, _, _, post = forward(dec, b, w)
     o = oracle.flood_f32(H, b.s, b.gamma, weights=w, max_iters=T, early_stop=False, want_Q_all=True)
     got = post.cpu().numpy()
@@ -69,13 +83,14 @@ def test_forward_matches_oracle(L):
     assert np.all(np.abs(post_a.cpu().numpy() - oa.Q_all) <= 1e-5 * np.maximum(np.abs(oa.Q_all), 1.0))
 
 
+@pytest.mark.parametrize("wlo", [0.4, -0.6])
 @pytest.mark.parametrize("L", [32, 64, 128])
-def test_backward_matches_oracle_adjoint(L):
+def test_backward_matches_oracle_adjoint(L, wlo):
     c, H, dec = code(L)
     b = noise.Batch(c.hz, 42, np.arange(24), 0.05)
     T = 5
     rng = np.random.default_rng(100 + L)
-    w = rng.uniform(0.4, 1.0, size=(T, c.hz.nnz)).astype(np.float32)
+    w = rng.uniform(wlo, 1.0, size=(T, c.hz.nnz)).astype(np.float32)
     G = rng.normal(size=(T, b.B, c.n)).astype(np.float32)
     syn, wt, ws, post = forward(dec, b, w)
     gw = torch.empty_like(wt)
@@ -115,12 +130,12 @@ def test_autograd_loss_gradient():
     assert np.all(np.abs(g - go) <= 1e-4 * ga + 1e-9)
 
 
-@pytest.mark.parametrize("L,p", [(32, 0.06), (64, 0.03)])
-def test_inference_with_fallback(L, p):
+@pytest.mark.parametrize("L,p,neg", [(32, 0.06, 0.0), (64, 0.03, 0.0), (64, 0.03, 0.002)])
+def test_inference_with_fallback(L, p, neg):
     c, H, dec = code(L)
     b = noise.Batch(c.hz, 44, np.arange(200), p)
     T = 8
-    w = np.random.default_rng(7).uniform(0.6, 0.9, size=(T, c.hz.nnz)).astype(np.float32)
+    w = weights(7, T, c.hz.nnz, 0.6, 0.9, neg)
     syn = to_dev(bits.pack_bits(b.s).view(np.int32))
     pr = to_dev(b.gamma)
     err, conv, it, _ = dec.outputs(b.B)
@@ -144,15 +159,15 @@ def test_inference_with_fallback(L, p):
     assert np.array_equal(it.cpu().numpy().astype(np.int32), want_i)
 
 
-@pytest.mark.parametrize("L,p", [(32, 0.06), (64, 0.04), (128, 0.04)])
-def test_inference_with_continuing_fallback(L, p):
+@pytest.mark.parametrize("L,p,neg", [(32, 0.06, 0.0), (64, 0.04, 0.0), (128, 0.04, 0.0), (64, 0.04, 0.002)])
+def test_inference_with_continuing_fallback(L, p, neg):
     """Neural weights in iterations 1..T, plain min-sum continuing from the
     neural messages up to 32 iterations: decisions, flags and iteration counts
     equal the oracle's, and the fallback flag marks iterations beyond T."""
     c, H, dec = code(L)
     b = noise.Batch(c.hz, 45, np.arange(160 if L < 128 else 64), p)
     T = 8
-    w = np.random.default_rng(8).uniform(0.6, 0.9, size=(T, c.hz.nnz)).astype(np.float32)
+    w = weights(8, T, c.hz.nnz, 0.6, 0.9, neg)
     syn = to_dev(bits.pack_bits(b.s).view(np.int32))
     pr = to_dev(b.gamma)
     err, conv, it, _ = dec.outputs(b.B)

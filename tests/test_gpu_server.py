@@ -1,7 +1,10 @@
 """Continuous-batching server: every request's result equals decoding it
 alone (plain min-sum through qldpc_decode_batch, neural min-sum through
 qldpc_nbp_decode) whatever else shares its micro-batch; admission refuses
-work beyond the queue and the HBM budget; the Poisson load generator runs."""
+work beyond the queue and the HBM budget; a micro-batch whose launch fails
+(failure injected on the host, before anything is enqueued) completes every
+affected request with an error status and leaves its buffers untouched; the
+Poisson load generator runs."""
 import time
 
 import numpy as np
@@ -142,5 +145,56 @@ def test_poisson_loadgen_runs():
         assert 0 < res["p50_us"] <= res["p99_us"] <= res["max_us"]
         assert lat.size == res["requests"] and np.all(lat > 0)
         print(res)
+    finally:
+        abi.qldpc_server_destroy(srv)
+
+
+def test_failed_launch_completes_with_error(monkeypatch):
+    st = setup()
+    prm = st["decs"][0].params(max_iters=32)
+    code = st["codes"][1]
+    with pytest.raises(abi.QldpcError) as ei:            # no neural kernel for L = 16
+        c16 = Decoder(lp.lp_code(16).hz)
+        abi.qldpc_server_create([c16.handle], prm, nms_weights=[st["w"][0]], nms_T=T, max_batch_shots=64)
+    assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED
+    monkeypatch.setenv("QLDPC_TEST_FAIL_LAUNCH", "2")    # the second micro-batch fails to launch
+    srv = abi.qldpc_server_create([d.handle for d in st["decs"]], prm, max_inflight=1, max_batch_shots=64,
+                                  queue_capacity=100)
+    monkeypatch.delenv("QLDPC_TEST_FAIL_LAUNCH")
+    try:
+        nreq = 6
+        reqs, submitted = [], []
+        for i in range(nreq):
+            b = noise.Batch(code.hz, 300 + i, np.arange(64), 0.03)
+            syn = np.ascontiguousarray(bits.pack_bits(b.s))
+            pr = np.ascontiguousarray(b.gamma)
+            err = np.full((64, (code.n + 31) // 32), 0xABABABAB, np.uint32)
+            conv = np.full(64, 7, np.uint8)
+            it = np.full(64, 7, np.uint8)
+            reqs.append((syn, pr, err, conv, it))
+            try:
+                abi.qldpc_server_submit(srv, 1, 0, 64, syn, pr, err, conv, it, req_id=i)
+                submitted.append(i)
+            except abi.QldpcError as e:              # submitted after the failure
+                assert e.status == abi.QLDPC_ERR_DEVICE
+        got = {}
+        t0 = time.time()
+        status = abi.QLDPC_OK
+        while len(got) < len(submitted) and time.time() - t0 < 30:
+            out, status = abi.qldpc_server_poll(srv, raise_errors=False)
+            for q in out:
+                got[q.req_id] = q.status
+            time.sleep(0.001)
+        assert sorted(got) == submitted
+        assert status == abi.QLDPC_ERR_DEVICE
+        assert got[0] == abi.QLDPC_OK
+        e1, c1, i1 = alone(st, 1, 0, reqs[0][0], reqs[0][1])
+        assert np.array_equal(reqs[0][2], e1) and np.array_equal(reqs[0][3], c1)
+        for i in submitted[1:]:
+            assert got[i] == abi.QLDPC_ERR_DEVICE
+            assert np.all(reqs[i][2] == 0xABABABAB) and np.all(reqs[i][3] == 7) and np.all(reqs[i][4] == 7)
+        with pytest.raises(abi.QldpcError) as ei:
+            abi.qldpc_server_submit(srv, 1, 0, 64, reqs[0][0], reqs[0][1], req_id=99)
+        assert ei.value.status == abi.QLDPC_ERR_DEVICE
     finally:
         abi.qldpc_server_destroy(srv)

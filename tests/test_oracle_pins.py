@@ -145,9 +145,9 @@ def test_first_iteration_closed_form_fp32_and_weights():
                 acc = np.float32(acc + (-a if b.s[sh, mm] else a))
             want[nn] = acc
         assert np.array_equal(r.Q[sh], want)
-    # per-edge weights: edge index = row-major position of (m, n)
+    # per-edge weights of both signs: edge index = row-major position of (m, n)
     rng = np.random.default_rng(3)
-    w = rng.uniform(0.3, 1.0, size=(1, c.hz.nnz)).astype(np.float32)
+    w = rng.uniform(-1.0, 1.0, size=(1, c.hz.nnz)).astype(np.float32)
     rw = oracle.flood_f32(H, b.s[:2], np.float32(gam), weights=w, max_iters=1, early_stop=False)
     eidx = -np.ones(H.shape, np.int64)
     eidx[np.nonzero(H)] = np.arange(c.hz.nnz)
@@ -384,14 +384,17 @@ def test_neural_then_plain_continuation():
         assert np.array_equal(rc.Q_all[k - 1, i] < 0, re.e[i].astype(bool))
 
 
-def test_neural_adjoint_matches_finite_differences():
+@pytest.mark.parametrize("wlo", [0.5, -1.0])
+def test_neural_adjoint_matches_finite_differences(wlo):
+    """Positive weights, and weights of mixed sign (a negative weight flips
+    its edge's message; the map stays linear in each weight)."""
     rng = np.random.default_rng(21)
     c = lp.lp_code(16)
     H = c.hz.dense()
     b = noise.Batch(c.hz, 14, np.arange(3), 0.06)
     T = 4
     nnz = c.hz.nnz
-    w = rng.uniform(0.5, 1.0, size=(T, nnz))
+    w = rng.uniform(wlo, 1.0, size=(T, nnz))
     prior = b.gamma.astype(np.float64)
     G = rng.normal(size=(T, b.B, c.n))
     Qa, qt = oracle.nms_forward_f64(H, b.s, prior, w)

@@ -36,8 +36,9 @@ class MixedBatch:
             self.e[c] = (idx, e)
             self.s[c] = s
             pk = bits.pack_bits(s)
-            for j, i in enumerate(idx):
-                self.syn[self.syn_off[i]:self.syn_off[i] + sw[c]] = pk[j]
+            if idx.size:
+                pos = self.syn_off[idx][:, None] + np.arange(sw[c])[None, :]
+                self.syn[pos] = pk
 
     def split_errors(self, err_words: np.ndarray):
         """Per code: decision bits [k, n] of that code's shots, in shot order."""
@@ -45,7 +46,7 @@ class MixedBatch:
         for c, sd in enumerate(self.sides):
             idx = self.e[c][0]
             ew = (sd.n + 31) // 32
-            rows = np.stack([err_words[self.err_off[i]:self.err_off[i] + ew] for i in idx]) if idx.size else \
+            rows = err_words[self.err_off[idx][:, None] + np.arange(ew)[None, :]] if idx.size else \
                 np.zeros((0, ew), np.uint32)
             out[c] = bits.unpack_bits(rows, sd.n)
         return out

@@ -20,14 +20,35 @@ from . import rng
 from .bits import pack_bits
 
 
-def errors(seed: int, shots, n: int, p) -> np.ndarray:
-    """uint8 [len(shots), n] Bernoulli(p) error bits; p scalar or per shot."""
+def _workers() -> int:
+    import os
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
+def errors(seed: int, shots, n: int, p, chunk: int = 1024) -> np.ndarray:
+    """uint8 [len(shots), n] Bernoulli(p) error bits; p scalar or per shot.
+
+    Row blocks are drawn on a few threads (numpy releases the interpreter
+    lock in its array loops); each value depends only on (seed, shot, bit)."""
     shots = np.asarray(shots, dtype=np.int64)
-    u = rng.uniform_rows(seed, rng.DOMAIN_ERROR, shots, n)
-    p = np.asarray(p, dtype=np.float64)
-    if p.ndim == 1:
-        p = p[:, None]
-    return (u < p).astype(np.uint8)
+    p = np.broadcast_to(np.asarray(p, dtype=np.float64), shots.shape)
+    out = np.empty((shots.size, n), dtype=np.uint8)
+
+    def block(lo):
+        hi = min(lo + chunk, shots.size)
+        u = rng.uniform_rows(seed, rng.DOMAIN_ERROR, shots[lo:hi], n, chunk=chunk)
+        out[lo:hi] = u < p[lo:hi, None]
+
+    starts = range(0, shots.size, chunk)
+    if shots.size <= chunk:
+        for lo in starts:
+            block(lo)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(_workers()) as ex:
+            list(ex.map(block, starts))
+    return out
 
 
 def syndromes(side, e: np.ndarray, chunk: int = 2048) -> np.ndarray:
@@ -35,7 +56,8 @@ def syndromes(side, e: np.ndarray, chunk: int = 2048) -> np.ndarray:
     B = e.shape[0]
     s = np.zeros((B, side.m), dtype=np.uint8)
     deg = np.diff(side.row_ptr)
-    for lo in range(0, B, chunk):
+
+    def block(lo):
         blk = e[lo:lo + chunk]
         if np.all(deg == deg[0]):
             g = blk[:, side.col_idx].reshape(blk.shape[0], side.m, int(deg[0]))
@@ -44,6 +66,15 @@ def syndromes(side, e: np.ndarray, chunk: int = 2048) -> np.ndarray:
             for r in range(side.m):
                 cols = side.col_idx[side.row_ptr[r]:side.row_ptr[r + 1]]
                 s[lo:lo + chunk, r] = np.bitwise_xor.reduce(blk[:, cols], axis=1) if cols.size else 0
+
+    starts = range(0, B, chunk)
+    if B <= chunk:
+        for lo in starts:
+            block(lo)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(_workers()) as ex:
+            list(ex.map(block, starts))
     return s
 
 
