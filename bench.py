@@ -77,6 +77,12 @@ def main():
     ap.add_argument("--mixed-shots", type=int, default=262144, help="mixed-code batch size (0 = skip)")
     ap.add_argument("--hbm-shots", type=int, default=8192,
                     help="shots of the L=256 code decoded with messages in HBM (0 = skip)")
+    ap.add_argument("--nms-train-shots", type=int, default=1 << 20,
+                    help="training pairs of the neural min-sum study at p = 0.05 (0 = skip the study)")
+    ap.add_argument("--nms-epochs", type=int, default=4)
+    ap.add_argument("--nms-eval-shots", type=int, default=1 << 18)
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="seconds of open-loop load per offered rate of the serving sweep (0 = skip)")
     ap.add_argument("--seed", type=int, default=20250807)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run one plain device copy of MIB MiB (a known-size "
@@ -263,6 +269,9 @@ def main():
             abi.qldpc_mixed_destroy(plan)
 
     # ---------------- large lift: edge messages in HBM --------------------------
+    # L = 256 messages do not fit on chip: they sit in a device workspace and
+    # every iteration streams them through HBM, so the message format sets the
+    # bytes moved (4, 2 or 1 per message; Table 1's reduced-precision formats).
     hbm = None
     if args.hbm_shots > 0:
         Lh, Bh = 256, args.hbm_shots
@@ -272,34 +281,43 @@ def main():
         bh = noise.Batch(ch.hz, args.seed + 77, np.arange(Bh), 0.03)
         gen_h = time.time() - t0h
         syn_h = torch.from_numpy(bits.pack_bits(bh.s).view(np.int32)).to(dev)
-        pr_h = torch.from_numpy(bh.gamma).to(dev)
-        prm = dh.params(layout=abi.QLDPC_LAYOUT_HBM)
-        need = abi.qldpc_decode_workspace_bytes(dh.handle, prm, Bh)
-        ws = torch.empty(need, dtype=torch.uint8, device=dev)
-        outh = dh.outputs(Bh)
+        priors_h = {abi.QLDPC_F32: torch.from_numpy(bh.gamma).to(dev),
+                    abi.QLDPC_I8Q4: torch.from_numpy(bh.gamma_q4()).to(dev),
+                    abi.QLDPC_I16Q8: torch.from_numpy(bh.gamma_q8()).to(dev)}
+        io_h = (ch.hz.m + 31) // 32 * 4 + 4 + (ch.hz.n + 31) // 32 * 4 + 2
+        hbm = dict(code=f"LP 3x5, L={Lh} (N={ch.hz.n}, E={ch.hz.nnz})", shots=Bh, p=0.03,
+                   layout="workgroup per shot (8 waves), edge messages in an HBM workspace",
+                   input_generation_s=gen_h, formats={})
+        for fname, fmt, bpm, traffic_file in (("f32", abi.QLDPC_F32, 4, "traffic_k_hbm_f32_L256.json"),
+                                              ("int16", abi.QLDPC_I16Q8, 2, "traffic_k_hbm_i16_L256.json"),
+                                              ("int8", abi.QLDPC_I8Q4, 1, "traffic_k_hbm_i8_L256.json")):
+            prm = dh.params(fmt=fmt, layout=abi.QLDPC_LAYOUT_HBM)
+            need = abi.qldpc_decode_workspace_bytes(dh.handle, prm, Bh)
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            outh = dh.outputs(Bh)
+            pr_h = priors_h[fmt]
 
-        def run_h():
-            abi.qldpc_decode_batch_ws(dh.handle, prm, Bh, syn_h, pr_h, *outh[:3], None, ws, need, stream)
+            def run_h():
+                abi.qldpc_decode_batch_ws(dh.handle, prm, Bh, syn_h, pr_h, *outh[:3], None, ws, need, stream)
 
-        run_h()
-        torch.cuda.synchronize()
-        e0h, e1h = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0h.record(stream)
-        for _ in range(3):
             run_h()
-        e1h.record(stream)
-        torch.cuda.synchronize()
-        ms_h = e0h.elapsed_time(e1h) / 3
-        its_h = int(outh[2].to(torch.int64).sum().item())
-        edge_h = its_h * edge_model_bytes(ch.hz.nnz, 4) + Bh * ((ch.hz.m + 31) // 32 * 4 + 4 + (ch.hz.n + 31) // 32 * 4 + 2)
-        hbm = dict(value=Bh / (ms_h * 1e-3), unit="syndromes/s", code=f"LP 3x5, L={Lh} (N={ch.hz.n}, E={ch.hz.nnz})",
-                   shots=Bh, p=0.03, dtype="f32", ms_per_launch=ms_h, mean_iters=its_h / Bh,
-                   converged=float(outh[1].float().mean().item()), workspace_bytes=need,
-                   edge_model_GBps=edge_h / (ms_h * 1e-3) / 1e9,
-                   edge_model_frac=edge_h / (ms_h * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                   hbm_traffic=recorded_traffic(None, "traffic_k_hbm_f32_L256.json"),
-                   layout="workgroup per shot (8 waves), edge messages in an HBM workspace", input_generation_s=gen_h)
-        del ws
+            torch.cuda.synchronize()
+            e0h, e1h = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0h.record(stream)
+            for _ in range(3):
+                run_h()
+            e1h.record(stream)
+            torch.cuda.synchronize()
+            ms_h = e0h.elapsed_time(e1h) / 3
+            its_h = int(outh[2].to(torch.int64).sum().item())
+            edge_h = its_h * edge_model_bytes(ch.hz.nnz, bpm) + Bh * io_h
+            hbm["formats"][fname] = dict(
+                value=Bh / (ms_h * 1e-3), unit="syndromes/s", bytes_per_message=bpm, ms_per_launch=ms_h,
+                mean_iters=its_h / Bh, converged=float(outh[1].float().mean().item()), workspace_bytes=need,
+                edge_model_bytes_per_launch=edge_h, edge_model_GBps=edge_h / (ms_h * 1e-3) / 1e9,
+                edge_model_frac=edge_h / (ms_h * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                hbm_traffic_bytes_per_launch=recorded_traffic(None, traffic_file))
+            del ws
 
     # ---------------- latency: one syndrome per request, host to host ---------
     latency = None
@@ -375,6 +393,43 @@ def main():
                                  "per request (p = 0.01), one workgroup per syndrome; both_css_sides: one "
                                  "request = the H_Z syndrome of X errors and the H_X syndrome of independent Z "
                                  "errors at the same rate, decoded together by one resident grid")
+
+    # ---------------- neural min-sum: trained in-run, judged by plain min-sum ----
+    neural = None
+    if args.nms_train_shots > 0 and args.L == 64:
+        from paper_2508_07879_amd import train_nms
+        t0n = time.time()
+        neural = train_nms.study(dec, code, side, dev, Ts=(8, 16), p=0.05, train_shots=args.nms_train_shots,
+                                 epochs=args.nms_epochs, eval_shots=args.nms_eval_shots,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+        ev = neural["eval"]
+        ref = ev["ms_32"]
+        best = min((k for k in ev if k.startswith("nms_")), key=lambda k: ev[k]["ler"])
+        neural["summary"] = dict(
+            plain_32=dict(ler=ref["ler"], mean_iters=ref["mean_iters"], syndromes_per_s=ref["syndromes_per_s"]),
+            best_neural=best, best=dict(ler=ev[best]["ler"], ci95=ev[best]["ci95"], mean_iters=ev[best]["mean_iters"],
+                                        syndromes_per_s=ev[best]["syndromes_per_s"]),
+            lower_ler_in_fewer_iterations=bool(ev[best]["ci95"][1] < ref["ci95"][0]
+                                               and ev[best]["mean_iters"] < ref["mean_iters"]),
+            throughput_ratio=ev[best]["syndromes_per_s"] / ref["syndromes_per_s"])
+        neural["wall_s"] = time.time() - t0n
+        neural["definition"] = ("weights [T][7680] trained at their own T from all-alpha on the same seeded "
+                                "(error, syndrome) pairs at p = 0.05 (BCE on sigma(-Q) over all T "
+                                "iterations, Adam, batch 4096), evaluated on held-out seeds; *_fallback = "
+                                "plain min-sum from scratch for shots not converged after T neural "
+                                "iterations; *_continue = plain min-sum continues from the neural messages "
+                                "up to 32 iterations in all; ms_16 / ms_32 = plain min-sum")
+
+    # ---------------- serving: continuous batching under Poisson load ----------
+    serving = None
+    if args.serve_seconds > 0 and args.L == 64:
+        from paper_2508_07879_amd import serve
+        serving = serve.main(["--L", "32", "64", "128", "--rates", "1e3", "1e5", "1e6", "2e6",
+                              "--duration", str(args.serve_seconds)])
+        serving["definition"] = ("open-loop Poisson arrivals of 1- and 64-shot requests (half each) over the "
+                                 "L = 32, 64, 128 codes, plain or neural decoder (half each; untrained weights "
+                                 "= all alpha, flagged), per-shot p ~ U[0.01, 0.08]; latency from scheduled "
+                                 "arrival to completion")
 
     # ---------------- CPU oracle on a bounded sample ---------------------------
     cpu = None
@@ -470,6 +525,8 @@ def main():
                      "(LDS in the comparison layout), so HBM carries only the I/O",
         },
         "latency_us": latency,
+        "neural_min_sum": neural,
+        "serving": serving,
         "mixed_batch": mixed,
         "large_lift_hbm": hbm,
         "pcie_inclusive": pcie,

@@ -358,6 +358,12 @@ qldpc_status qldpc_code_create(const qldpc_code_desc *d, int32_t device, qldpc_c
             }
             host.lowmask[R * 8 + j] = low;
         }
+    for (int C = 0; C < T.ncols(); ++C)
+        for (int i = 0; i < T.col_deg[C]; ++i) {
+            const int slot = T.col_R[C][i] * 8 + T.col_j[C][i];
+            const int32_t s = host.shift[slot], c = (L - s) % L;
+            host.colrot[C][i] = ColRot{s, c, 4 * c, 4 * s, host.lowmask[slot], 0};
+        }
     int prev = 0;
     hipError_t e = hipGetDevice(&prev);
     if (e != hipSuccess) { delete code; return hip_fail(e, "hipGetDevice"); }

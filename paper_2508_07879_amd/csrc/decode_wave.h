@@ -145,6 +145,18 @@ __device__ __forceinline__ void rotr128(uint64_t lo, uint64_t hi, uint32_t s, ui
     ohi = (hi >> s) | ((lo << 1) << (63u - s));
 }
 
+// gfx950's three-input bitwise operation: bit i of the result is f(bit i of
+// a, bit i of b, bit i of c), f given by its truth table TT (the table of a
+// function is that function applied to 0xF0, 0xCC and 0xAA).
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t bitop3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+}
+constexpr uint32_t kXor3 = (0xF0u ^ 0xCCu ^ 0xAAu) & 0xFFu;       // a ^ b ^ c
+constexpr uint32_t kXorAnd = (0xF0u ^ (0xCCu & 0xAAu)) & 0xFFu;   // a ^ (b & c)
+constexpr uint32_t kOrAnd = (0xF0u | (0xCCu & 0xAAu)) & 0xFFu;    // a | (b & c)
+constexpr uint32_t kSign = 0x80000000u;
+
 __device__ __forceinline__ uint32_t fbits(float x) { return __float_as_uint(x); }
 __device__ __forceinline__ float ubits(uint32_t x) { return __uint_as_float(x); }
 __device__ __forceinline__ uint64_t ballot(bool b) { return __ballot(b); }
@@ -173,6 +185,38 @@ __device__ __forceinline__ int cn_index(int lane, int h, uint32_t s) {
 
 // ---- check-node rule, FP32 (Algorithm 1): r_j = (-1)^{s + sum_{i != j} neg_i}
 //      * fl(alpha * min_{i != j} |q_i|).  P carries s in bit 31 on entry.
+// Sign parity of a check: bit 31 of P ^ v_0 ^ ... ^ v_{DC-1} (three-input
+// XORs; the lower bits are don't-cares).
+template <int DC>
+__device__ __forceinline__ uint32_t sign_parity(const float (&v)[DC], uint32_t P) {
+    int j = 0;
+#pragma unroll
+    for (; j + 1 < DC; j += 2) P = bitop3<kXor3>(P, fbits(v[j]), fbits(v[j + 1]));
+    if (j < DC) P ^= fbits(v[j]);
+    return P;
+}
+
+// The outgoing messages of a check from its two candidate magnitudes A1
+// (not the minimum edge) and A2 (the minimum edge): the check sign P is put
+// on both once, then each edge flips it by its own sign bit, so an edge costs
+// a compare, a select and one three-input operation.
+template <int DC>
+__device__ __forceinline__ void cn_emit(float (&v)[DC], uint32_t P, float m1, float A1, float A2) {
+    const uint32_t B1 = bitop3<kOrAnd>(fbits(A1), P, kSign);
+    const uint32_t B2 = bitop3<kOrAnd>(fbits(A2), P, kSign);
+    // |q_j| == min1: j is the (or a tied) minimum; the excluded minimum is
+    // min2 (equal to min1 on a tie).  All compares first, so that no select
+    // waits on the compare just before it.
+    bool isMin[DC];
+#pragma unroll
+    for (int j = 0; j < DC; ++j) isMin[j] = fabsf(v[j]) == m1;
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        const uint32_t b = isMin[j] ? B2 : B1;
+        v[j] = ubits(bitop3<kXorAnd>(b, fbits(v[j]), kSign));
+    }
+}
+
 template <int DC>
 __device__ __forceinline__ void cn_f32(float (&v)[DC], uint32_t P, float alpha) {
     float m1 = fminf(fabsf(v[0]), fabsf(v[1]));
@@ -182,20 +226,13 @@ __device__ __forceinline__ void cn_f32(float (&v)[DC], uint32_t P, float alpha) 
         m2 = __builtin_amdgcn_fmed3f(m1, m2, fabsf(v[j]));
         m1 = fminf(m1, fabsf(v[j]));
     }
-#pragma unroll
-    for (int j = 0; j < DC; ++j) P ^= fbits(v[j]);
+    P = sign_parity<DC>(v, P);
     float A1 = alpha * m1;
     float A2 = alpha * m2;
     // two products per check: keep the compiler from moving the multiply
     // behind the per-edge select below (one product per edge)
     asm volatile("" : "+v"(A1), "+v"(A2));
-#pragma unroll
-    for (int j = 0; j < DC; ++j) {
-        // |q_j| == min1: j is the (or a tied) minimum; the excluded minimum is
-        // min2 (equal to min1 on a tie).
-        const float mag = (fabsf(v[j]) == m1) ? A2 : A1;
-        v[j] = ubits(fbits(mag) | ((P ^ fbits(v[j])) & 0x80000000u));
-    }
+    cn_emit<DC>(v, P, m1, A1, A2);
 }
 
 // ---- check-node rule, integer formats: magnitudes in [0, qmax], alpha =
@@ -248,16 +285,11 @@ __device__ __forceinline__ void cn_fxf(float (&v)[DC], uint32_t P, float alpha) 
         m2 = __builtin_amdgcn_fmed3f(m1, m2, fabsf(v[j]));
         m1 = fminf(m1, fabsf(v[j]));
     }
-#pragma unroll
-    for (int j = 0; j < DC; ++j) P ^= fbits(v[j]);
+    P = sign_parity<DC>(v, P);
     float A1 = floorf(alpha * m1);
     float A2 = floorf(alpha * m2);
     asm volatile("" : "+v"(A1), "+v"(A2));
-#pragma unroll
-    for (int j = 0; j < DC; ++j) {
-        const float mag = (fabsf(v[j]) == m1) ? A2 : A1;
-        v[j] = ubits(fbits(mag) | ((P ^ fbits(v[j])) & 0x80000000u));
-    }
+    cn_emit<DC>(v, P, m1, A1, A2);
 }
 
 template <int FMT>
@@ -278,6 +310,11 @@ __device__ __forceinline__ float bperm(int addr, float v) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
 __device__ __forceinline__ int bperm(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+// Forward permute: the lane whose byte address (4 * lane) is `addr` receives
+// `v` (addresses must form a permutation of the lanes).
+__device__ __forceinline__ float fperm(int addr, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_permute(addr, __float_as_int(v)));
+}
 
 }  // namespace wave
 
@@ -299,12 +336,14 @@ __device__ __forceinline__ void cn_f32_weighted(float (&v)[DC], uint32_t P, cons
         m2 = __builtin_amdgcn_fmed3f(m1, m2, fabsf(v[j]));
         m1 = fminf(m1, fabsf(v[j]));
     }
-#pragma unroll
-    for (int j = 0; j < DC; ++j) P ^= fbits(v[j]);
+    P = sign_parity<DC>(v, P);
+    // the check sign on both candidate minima: fl(w * (+-m)) = +-fl(w * m)
+    const float M1 = ubits(bitop3<kOrAnd>(fbits(m1), P, kSign));
+    const float M2 = ubits(bitop3<kOrAnd>(fbits(m2), P, kSign));
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
-        const float wm = wj[j] * ((fabsf(v[j]) == m1) ? m2 : m1);
-        v[j] = ubits(fbits(wm) ^ ((P ^ fbits(v[j])) & 0x80000000u));
+        const float wm = wj[j] * ((fabsf(v[j]) == m1) ? M2 : M1);
+        v[j] = ubits(bitop3<kXorAnd>(fbits(wm), fbits(v[j]), kSign));
     }
 }
 
@@ -420,6 +459,18 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
         if constexpr (L == 64) return (int)(lane4 + (s << 2));
         else return (int)(((lane4 + (s << 2)) & (uint32_t)(4 * L - 4)) | (lane4 & ~(uint32_t)(4 * L - 1)));
     };
+    // REG flooding, edge i of block column C: the byte address of lane
+    // (t + c) mod L = (t - s) mod L, whose check meets this lane's variable.
+    // The variable pass reads the message there (ds_bpermute) and sends the
+    // new one back to the same lane (ds_permute), one address for both.
+    auto vn_lane = [&](int C, int i) -> int {
+        // lane4 + 4c in one vector instruction from the scalar c
+        const uint32_t c = (uint32_t)cpb->colrot[C][i].c;
+        uint32_t d;
+        asm("v_mad_u32_u24 %0, %1, 4, %2" : "=v"(d) : "s"(c), "v"(lane4));
+        if constexpr (L == 64) return (int)d;
+        else return (int)((d & (uint32_t)(4 * L - 4)) | (lane4 & ~(uint32_t)(4 * L - 1)));
+    };
 
     bool valid[NG];
     bool any_valid = false;
@@ -508,11 +559,27 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
 
     for (int k = 1; k <= a.max_iters; ++k) {
         __builtin_amdgcn_wave_barrier();
+        // Syndrome accumulators of the block rows, seeded with the rows'
+        // syndrome ballots.  REG: seeded after the check pass from an opaque
+        // copy of sb, so the ballots are re-derived every iteration instead
+        // of being hoisted out of the loop, where they would pin 2 * MB scalar
+        // registers for its whole length.
         uint64_t acc[MB][H];
+        auto seed_acc = [&]() {
+            uint32_t sbo[H];
 #pragma unroll
-        for (int R = 0; R < MB; ++R)
+            for (int h = 0; h < H; ++h) {
+                sbo[h] = sb[h];
+                if constexpr (REG) asm volatile("" : "+v"(sbo[h]));
+            }
 #pragma unroll
-            for (int h = 0; h < H; ++h) acc[R][h] = ballot(((sb[h] >> R) & 1u) != 0);
+            for (int R = 0; R < MB; ++R)
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    acc[R][h] = ballot(((sbo[h] >> R) & 1u) != 0);
+                }
+        };
+        if constexpr (!REG) seed_acc();
 #pragma unroll
         for (int h = 0; h < H; ++h) eb[h] = 0;
 
@@ -593,8 +660,8 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                         constexpr int j = decltype(Jc)::value;
                         constexpr int C = S::T.slot_bc[R][j];
                         m[R * DC + j] = c[j];
-                        // the variable at position t receives the value of check t - s
-                        Qv[C] = bperm(vn_src(shift_of(R * DC + j)), v[j] + c[j]);
+                        // the variable at position t + s receives the value of check t
+                        Qv[C] = fperm(cn_src(shift_of(R * DC + j)), v[j] + c[j]);
                     });
                     return;
                 }
@@ -641,6 +708,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
             __builtin_amdgcn_wave_barrier();
         }
 
+        if constexpr (REG) seed_acc();
         // ---------------- variable nodes, a posteriori, decision -------------
         // Block columns are processed Knobs::vn_batch at a time: every message
         // of the batch is loaded before any is overwritten, so the rotated
@@ -664,7 +732,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                             constexpr int i = decltype(Ii)::value;
                             constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
                             if constexpr (REG) {
-                                rr[kc][h][i] = bperm(vn_src(shift_of(slot)), m[slot]);
+                                rr[kc][h][i] = bperm(vn_lane(C, i), m[slot]);
                             } else {
                                 ii[kc][h][i] = slot * ROW + vn_at(h, (uint32_t)code->shift[slot]);
                                 rr[kc][h][i] = (acc_t)msg[ii[kc][h][i]];
@@ -702,7 +770,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                                 static_for<0, d>([&](auto Ii) {
                                     constexpr int i = decltype(Ii)::value;
                                     constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
-                                    m[slot] = bperm(cn_src(shift_of(slot)), qv[i]);
+                                    m[slot] = fperm(vn_lane(C, i), qv[i]);
                                 });
                             } else {
 #pragma unroll
@@ -717,7 +785,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                             static_for<0, d>([&](auto Ii) {
                                 constexpr int i = decltype(Ii)::value;
                                 constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
-                                m[slot] = bperm(cn_src(shift_of(slot)), satf<FMT>(sum - r[i]));
+                                m[slot] = fperm(vn_lane(C, i), satf<FMT>(sum - r[i]));
                             });
                             Q = sum;
                         } else {
@@ -728,7 +796,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                                 static_for<0, d>([&](auto Ii) {
                                     constexpr int i = decltype(Ii)::value;
                                     constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
-                                    m[slot] = (acc_t)bperm(cn_src(shift_of(slot)), sat<FMT>(sum - (int)r[i]));
+                                    m[slot] = (acc_t)__builtin_amdgcn_ds_permute(vn_lane(C, i), sat<FMT>(sum - (int)r[i]));
                                 });
                             } else {
 #pragma unroll
@@ -751,12 +819,22 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
                     constexpr int i = decltype(Ii)::value;
                     constexpr int R = S::T.col_R[C][i];
                     constexpr int slot = R * DC + S::T.col_j[C][i];
-                    const uint32_t s = shift_of(slot);
-                    if constexpr (GRP) {
-                        const uint64_t low = REG ? cpb->lowmask[slot] : code->lowmask[slot];
+                    if constexpr (REG) {
+                        // rotate right by s: (m >> s) | (m << c) within each segment
+                        const uint32_t s = (uint32_t)cpb->colrot[C][i].s, c = (uint32_t)cpb->colrot[C][i].c;
+                        if constexpr (L == 64) {
+                            acc[R][0] ^= (mask[0] >> s) | (mask[0] << c);
+                        } else {
+                            const uint64_t low = cpb->colrot[C][i].low;
+                            acc[R][0] ^= ((mask[0] >> s) & low) | ((mask[0] << c) & ~low);
+                        }
+                    } else if constexpr (GRP) {
+                        const uint32_t s = shift_of(slot);
+                        const uint64_t low = code->lowmask[slot];
 #pragma unroll
                         for (int h = 0; h < H; ++h) acc[R][h] ^= seg_rotr<L>(mask[h], s, low);
                     } else {
+                        const uint32_t s = shift_of(slot);
                         uint64_t lo, hi;
                         rotr128(mask[0], mask[H - 1], s, lo, hi);
                         acc[R][0] ^= lo;

@@ -8,9 +8,25 @@ namespace qldpc {
 constexpr int kMaxSlots = 120;   // block rows x check degree of the supported patterns
 
 // Per-code device table (one allocation per code object).
+constexpr int kMaxBlockCols = 34;   // block columns of the supported patterns
+constexpr int kMaxColDeg = 5;       // nonzero blocks per block column
+
+// Rotation data of one edge block, as the register-resident decoder reads it
+// per block column (block rows increasing): the shift s, its complement
+// c = (L - s) mod L, the byte offsets 4c and 4s of the cross-lane permutes
+// (variable t meets check t - s = t + c mod L), and the low-bits mask of the
+// segment rotation.
+struct ColRot {
+    int32_t s, c, c4, s4;
+    uint64_t low;
+    uint64_t pad;
+};
+
+// Per-code device table (one allocation per code object).
 struct DevCode {
     int32_t shift[kMaxSlots];     // circulant shift of slot (R, j), in [0, L)
     uint64_t lowmask[kMaxSlots];  // L < 64: per-segment mask of the low L - shift bits
+    ColRot colrot[kMaxBlockCols][kMaxColDeg];   // the same shifts by block column, L <= 64
 };
 
 // A DevCode seen through the constant address space.  No kernel writes the

@@ -36,6 +36,7 @@ struct PatternTables {
     int col_deg[34];         // nonzero blocks in block column C
     int col_R[34][kMaxDv];   // their block rows, increasing
     int col_j[34][kMaxDv];   // their slot index within that block row
+    constexpr int ncols() const { return 34; }
 };
 
 // which = 0: H_Z side, 1: H_X side.

@@ -81,7 +81,7 @@ def main(argv=None):
             res, _ = abi.qldpc_server_loadgen(srv, r, args.duration, pools_s, pools_p, seed=int(r) % 1000003)
             res["offered_shots_per_s"] = r
             out["points"].append(res)
-            print(json.dumps(res), flush=True)
+            print(json.dumps(res), file=sys.stderr, flush=True)
     finally:
         abi.qldpc_server_destroy(srv)
     if args.json:
