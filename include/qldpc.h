@@ -218,6 +218,27 @@ qldpc_status qldpc_decode_batch_ws(qldpc_code code, const qldpc_decode_params *p
                                    uint8_t *converged, uint8_t *iters_used, float *posterior, void *workspace,
                                    size_t workspace_bytes, void *stream);
 
+/* Bytes of the library's own message workspace on each device. */
+#define QLDPC_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * decode as qldpc_decode_batch_ws, with the message workspace taken from a
+ * buffer of QLDPC_STATIC_WORKSPACE_BYTES (64 MiB) that the library holds on
+ * each device until the process ends.  Allocates nothing.  Arguments,
+ * layouts and results are those of qldpc_decode_batch; layouts that keep
+ * messages on chip use no workspace.  A batch whose workspace
+ * (qldpc_decode_workspace_bytes) exceeds the buffer returns
+ * QLDPC_ERR_CAPACITY (e.g. at most 546 FP32 or 2184 int8 shots per call at
+ * L = 256).  The first call on a device looks up that device's buffer
+ * (hipGetSymbolAddress) with the device current.  Every call on a device
+ * shares its one buffer: calls that overlap on one device (other streams or
+ * threads) race, and the caller must serialise them. */
+qldpc_status qldpc_decode_batch_static(qldpc_code code, const qldpc_decode_params *params, int32_t batch,
+                                       const uint32_t *syndromes, const void *priors, uint32_t *errors,
+                                       uint8_t *converged, uint8_t *iters_used, float *posterior,
+                                       void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Layout autotuner                                                          */
 /* ------------------------------------------------------------------------ */

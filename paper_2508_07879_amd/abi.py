@@ -102,6 +102,7 @@ def _load():
         "qldpc_decode_workspace_bytes": ([vp, C.POINTER(qldpc_decode_params), i32, C.POINTER(C.c_size_t)], i32),
         "qldpc_decode_batch_ws": ([vp, C.POINTER(qldpc_decode_params), i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t,
                                    vp], i32),
+        "qldpc_decode_batch_static": ([vp, C.POINTER(qldpc_decode_params), i32, vp, vp, vp, vp, vp, vp, vp], i32),
         "qldpc_autotune": ([vp, C.POINTER(qldpc_decode_params), i32, vp, vp, vp, vp, vp, vp,
                             C.POINTER(qldpc_decode_params)], i32),
         "qldpc_tune_save": ([vp, C.c_char_p], i32),
@@ -235,6 +236,16 @@ def qldpc_decode_batch_ws(h, params: qldpc_decode_params, batch: int, syndromes,
     _check(lib.qldpc_decode_batch_ws(h, C.byref(params), int(batch), _ptr(syndromes), _ptr(priors), _ptr(errors),
                                      _ptr(converged), _ptr(iters_used), _ptr(posterior), _ptr(workspace),
                                      int(workspace_bytes), _stream(stream)))
+
+
+QLDPC_STATIC_WORKSPACE_BYTES = 64 << 20
+
+
+def qldpc_decode_batch_static(h, params: qldpc_decode_params, batch: int, syndromes, priors, errors,
+                              converged, iters_used=None, posterior=None, stream=None) -> None:
+    _check(lib.qldpc_decode_batch_static(h, C.byref(params), int(batch), _ptr(syndromes), _ptr(priors),
+                                         _ptr(errors), _ptr(converged), _ptr(iters_used), _ptr(posterior),
+                                         _stream(stream)))
 
 
 def qldpc_autotune(h, params: qldpc_decode_params, batch: int, syndromes, priors, errors, converged,
