@@ -34,49 +34,138 @@ struct MixedArgs {
     const int64_t *err_off;                // [batch], words into err
     const uint32_t *syn;
     uint32_t *err;
-    int32_t *scratch;                      // counts[8], cursors[8], tile counters[8], order[batch]
+    int32_t *scratch;                      // see the mix:: accessors; then order[batch]
     int32_t batch;
 };
 
 namespace mix {
 
-__device__ __forceinline__ int32_t *counts(const MixedArgs &m) { return m.scratch; }
-__device__ __forceinline__ int32_t *cursors(const MixedArgs &m) { return m.scratch + kMaxMixCodes; }
 constexpr int kMixGrids = 8;   // one persistent grid per (pattern, lift size 16 / 32 / 64 / 128)
-constexpr int kScratchHead = 2 * kMaxMixCodes + kMixGrids;
+
+// Per-grid tile table, written by k_mix_plan: the codes of the grid in bucket
+// order, each with its first index into the order list, its shot count and
+// the running tile count at its end.
+struct GridEntry {
+    int32_t code, first, count, tiles_end;
+};
+
+// Scratch head (int32 words): counts[8] | cursors[8] | tile counters[8] |
+// order offset per code[8] | entries per grid[8] | grid tables[8][8] |
+// device code table pointers[8]; then the order list.
+constexpr int kCounts = 0, kCursors = 8, kTiles = 16, kOffs = 24, kNEnt = 32, kEnt = 40;
+constexpr int kCodePtr = kEnt + kMixGrids * kMaxMixCodes * 4;       // 8-byte aligned (296)
+constexpr int kScratchHead = kCodePtr + 2 * kMaxMixCodes;
+
+__device__ __forceinline__ int32_t *counts(const MixedArgs &m) { return m.scratch + kCounts; }
+__device__ __forceinline__ int32_t *cursors(const MixedArgs &m) { return m.scratch + kCursors; }
+__device__ __forceinline__ int32_t *offs(const MixedArgs &m) { return m.scratch + kOffs; }
+__device__ __forceinline__ int32_t *n_entries(const MixedArgs &m) { return m.scratch + kNEnt; }
+__device__ __forceinline__ GridEntry *entries(const MixedArgs &m, int g) {
+    return reinterpret_cast<GridEntry *>(m.scratch + kEnt) + g * kMaxMixCodes;
+}
+__device__ __forceinline__ const DevCode **code_table(const MixedArgs &m) {
+    return reinterpret_cast<const DevCode **>(m.scratch + kCodePtr);
+}
 
 __host__ __device__ __forceinline__ int grid_of(int which, int L) {
     return 4 * which + (L == 16 ? 0 : L == 32 ? 1 : L == 64 ? 2 : 3);
 }
 __device__ __forceinline__ int32_t *tile_ctr(const MixedArgs &m, int which, int L) {
-    return m.scratch + 2 * kMaxMixCodes + grid_of(which, L);
+    return m.scratch + kTiles + grid_of(which, L);
 }
 __device__ __forceinline__ int32_t *order(const MixedArgs &m) { return m.scratch + kScratchHead; }
 __host__ __device__ constexpr int shots_per_tile(int L) { return L <= 64 ? 64 / L : 1; }
 
+// Locates tile t of grid g (spt shots per tile) in the grid's table: the
+// code, the first index into the order list, the shot count; c = -1 once t
+// is past the last tile.  Reads the table from device memory each time (the
+// persistent loops call it after claiming a tile with an atomic, so nothing
+// of it stays in scalar registers across a decode).
+__device__ __forceinline__ void locate(const MixedArgs &m, int g, int spt, int t, int &c, int &first, int &cnt) {
+    c = -1;
+    first = cnt = 0;
+    const int ne = __builtin_amdgcn_readfirstlane(n_entries(m)[g]);
+    const GridEntry *E = entries(m, g);
+    int start = 0;
+    for (int k = 0; k < ne; ++k) {
+        const int end = __builtin_amdgcn_readfirstlane(E[k].tiles_end);
+        if (t < end) {
+            c = __builtin_amdgcn_readfirstlane(E[k].code);
+            const int n = __builtin_amdgcn_readfirstlane(E[k].count);
+            first = __builtin_amdgcn_readfirstlane(E[k].first) + (t - start) * spt;
+            cnt = min(spt, n - (t - start) * spt);
+            return;
+        }
+        start = end;
+    }
+}
+
 }  // namespace mix
 
 __global__ void k_mix_clear(const MixedArgs m) {
-    if (threadIdx.x < mix::kScratchHead) m.scratch[threadIdx.x] = 0;
+    const int i = threadIdx.x;
+    if (i < mix::kOffs) m.scratch[i] = 0;                    // counts, cursors, tile counters
+    if (i < kMaxMixCodes) mix::code_table(m)[i] = i < m.ncodes ? m.codes[i] : nullptr;
 }
 
-__global__ void k_mix_count(const MixedArgs m) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.batch) return;
-    const int c = m.shot_code[i];
-    if (c >= 0 && c < m.ncodes) atomicAdd(&mix::counts(m)[c], 1);
+// Counts shots per code: a workgroup histogram in LDS over a grid-stride
+// range of shots, then one global atomic per code per workgroup.
+constexpr int kBucketThreads = 1024;
+
+__global__ __launch_bounds__(kBucketThreads) void k_mix_count(const MixedArgs m) {
+    __shared__ int h[kMaxMixCodes];
+    if (threadIdx.x < kMaxMixCodes) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m.batch; i += gridDim.x * blockDim.x) {
+        const int c = m.shot_code[i];
+        if (c >= 0 && c < m.ncodes) atomicAdd(&h[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxMixCodes && h[threadIdx.x] > 0) atomicAdd(&mix::counts(m)[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_mix_scatter(const MixedArgs m) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.batch) return;
-    const int c = m.shot_code[i];
-    if (c < 0 || c >= m.ncodes) return;
-    int off = 0;
-    for (int d = 0; d < m.ncodes; ++d)
-        if (m.rank[d] < m.rank[c]) off += mix::counts(m)[d];
-    const int pos = off + atomicAdd(&mix::cursors(m)[c], 1);
-    mix::order(m)[pos] = i;
+// Order offsets per code (codes in bucket order: largest L first) and the
+// per-grid tile tables.  One wave.
+__global__ void k_mix_plan(const MixedArgs m) {
+    if (threadIdx.x != 0) return;
+    int tiles[mix::kMixGrids] = {}, ne[mix::kMixGrids] = {};
+    for (int r = 0, acc = 0; r < m.ncodes; ++r) {
+        int cc = 0;
+        for (int d = 0; d < m.ncodes; ++d)
+            if (m.rank[d] == r) cc = d;
+        const int n = mix::counts(m)[cc];
+        mix::offs(m)[cc] = acc;
+        const int g = mix::grid_of(m.which[cc], m.L[cc]);
+        const int spt = mix::shots_per_tile(m.L[cc]);
+        tiles[g] += (n + spt - 1) / spt;
+        mix::entries(m, g)[ne[g]++] = mix::GridEntry{cc, acc, n, tiles[g]};
+        acc += n;
+    }
+    for (int g = 0; g < mix::kMixGrids; ++g) mix::n_entries(m)[g] = ne[g];
+}
+
+// Scatters shot indices into the code-ordered list.  Each workgroup takes
+// the same grid-stride range as in k_mix_count: it counts its shots per code
+// in LDS, reserves one block of positions per code with one global atomic,
+// then places every shot at its code's offset + the block base + a rank from
+// an LDS counter.  (The order of shots within a code is immaterial: every
+// shot's result depends only on its own inputs.)
+__global__ __launch_bounds__(kBucketThreads) void k_mix_scatter(const MixedArgs m) {
+    __shared__ int h[kMaxMixCodes], base[kMaxMixCodes], cur[kMaxMixCodes];
+    if (threadIdx.x < kMaxMixCodes) h[threadIdx.x] = cur[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m.batch; i += gridDim.x * blockDim.x) {
+        const int c = m.shot_code[i];
+        if (c >= 0 && c < m.ncodes) atomicAdd(&h[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxMixCodes)
+        base[threadIdx.x] = h[threadIdx.x] > 0 ? atomicAdd(&mix::cursors(m)[threadIdx.x], h[threadIdx.x]) : 0;
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m.batch; i += gridDim.x * blockDim.x) {
+        const int c = m.shot_code[i];
+        if (c >= 0 && c < m.ncodes) mix::order(m)[mix::offs(m)[c] + base[c] + atomicAdd(&cur[c], 1)] = i;
+    }
 }
 
 template <class S, int L>
@@ -96,17 +185,17 @@ __device__ __forceinline__ void mix_tile(const MixedArgs &m, int c, int first, i
     ref[0].shot = shot;
     ref[0].syn = m.syn + so;
     ref[0].err = m.err + eo;
-    wave_decode<S, L, 0, 0, false, false, false, 1, REG>(m.base, m.codes[c], ref, lds);
+    const DevCode *code = (const DevCode *)wave::uniform64((uint64_t)mix::code_table(m)[c]);
+    wave_decode<S, L, 0, 0, false, false, false, 1, REG>(m.base, code, ref, lds);
 }
 
-// Persistent decoder of the shots whose code has pattern S and lift size L.  A claimed
-// tile is located by a short scalar walk over the codes in bucket order, so
-// nothing but pointers stays live across tiles (the decoder body needs the
-// registers).  Waves per SIMD: three for L <= 32; two for L = 64, whose
-// body inside the persistent loop would spill within the iteration loop at
-// three (two measured 4 % faster); one 61 KB LDS wave for L = 128.
+// Persistent decoder of the shots whose code has pattern S and lift size L.
+// A claimed tile is located in the grid's table in device memory, so nothing
+// but pointers stays live across tiles (the decoder body needs the
+// registers).  Three waves per SIMD for L <= 64 (messages in registers), one
+// 61 KB LDS wave for L = 128.
 template <class S, int L>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(L <= 32 ? 3 : L == 64 ? 2 : 1)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(L <= 64 ? 3 : 1)))
 void k_mix_decode(const MixedArgs m) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[WaveLds<S, L, 0, 0, 1, (L <= 64)>::bytes];
     constexpr int spt = mix::shots_per_tile(L);
@@ -114,50 +203,10 @@ void k_mix_decode(const MixedArgs m) {
         int t = 0;
         if ((threadIdx.x & 63) == 0) t = atomicAdd(mix::tile_ctr(m, S::WHICH, L), 1);
         t = __builtin_amdgcn_readfirstlane(t);
-        int c = -1, first = 0, cnt = 0;
-        for (int r = 0, acc = 0, tiles = 0; r < m.ncodes; ++r) {
-            int cc = 0;
-            for (int d = 0; d < m.ncodes; ++d)
-                if (m.rank[d] == r) cc = d;
-            const int n = __builtin_amdgcn_readfirstlane(mix::counts(m)[cc]);
-            if (m.L[cc] == L && m.which[cc] == S::WHICH) {
-                const int nt = (n + spt - 1) / spt;
-                if (c < 0 && t < tiles + nt) {
-                    c = cc;
-                    first = acc + (t - tiles) * spt;
-                    cnt = min(spt, n - (t - tiles) * spt);
-                }
-                tiles += nt;
-            }
-            acc += n;
-        }
+        int c, first, cnt;
+        mix::locate(m, mix::grid_of(S::WHICH, L), spt, t, c, first, cnt);
         if (c < 0) return;   // every tile of this pattern and lift size is taken
         mix_tile<S, L>(m, c, first, cnt, lds);
-    }
-}
-
-// Locates tile t of the codes with pattern S::WHICH and lift L (spt shots
-// per tile) by a scalar walk over the bucket order: code c, first index into
-// the order list, shot count; c = -1 once t is past the last tile.
-template <class S, int L, int spt>
-__device__ __forceinline__ void mix_locate(const MixedArgs &m, int t, int &c, int &first, int &cnt) {
-    c = -1;
-    first = cnt = 0;
-    for (int r = 0, acc = 0, tiles = 0; r < m.ncodes; ++r) {
-        int cc = 0;
-        for (int d = 0; d < m.ncodes; ++d)
-            if (m.rank[d] == r) cc = d;
-        const int n = __builtin_amdgcn_readfirstlane(mix::counts(m)[cc]);
-        if (m.L[cc] == L && m.which[cc] == S::WHICH) {
-            const int nt = (n + spt - 1) / spt;
-            if (c < 0 && t < tiles + nt) {
-                c = cc;
-                first = acc + (t - tiles) * spt;
-                cnt = min(spt, n - (t - tiles) * spt);
-            }
-            tiles += nt;
-        }
-        acc += n;
     }
 }
 
@@ -177,12 +226,13 @@ __global__ __launch_bounds__(64 * kMixBlockWaves) void k_mix_block(const MixedAr
         const int t = __builtin_amdgcn_readfirstlane(tile);
         __syncthreads();   // everyone has read tile before it is claimed again
         int c, first, cnt;
-        mix_locate<S, L, 1>(m, t, c, first, cnt);
+        mix::locate(m, mix::grid_of(S::WHICH, L), 1, t, c, first, cnt);
         if (c < 0) return;   // every L = 128 tile of this pattern is taken
         const long shot = (long)(int64_t)wave::uniform64((uint64_t)(int64_t)mix::order(m)[first]);
         const int64_t so = (int64_t)wave::uniform64((uint64_t)m.syn_off[shot]);
         const int64_t eo = (int64_t)wave::uniform64((uint64_t)m.err_off[shot]);
-        block_decode<S, L, 0, NW, false, false>(m.base, m.codes[c], shot, m.syn + so, m.err + eo, lds);
+        const DevCode *code = (const DevCode *)wave::uniform64((uint64_t)mix::code_table(m)[c]);
+        block_decode<S, L, 0, NW, false, false>(m.base, code, shot, m.syn + so, m.err + eo, lds);
         __syncthreads();   // LDS reused by the next shot
     }
 }

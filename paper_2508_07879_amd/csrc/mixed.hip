@@ -20,6 +20,11 @@ struct qldpc_mixed_s {
     int32_t waves128 = 0;           // workgroups of the L = 128 grid (messages in LDS)
     bool has_grid[mix::kMixGrids] = {};   // (pattern, L) pairs among the plan's codes
     int32_t *scratch = nullptr;     // device
+    // The L = 128 workgroup grids run on a second stream, forked from and
+    // joined back into the caller's (or the capture) stream, so that they
+    // overlap the register grids instead of running before them.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::mutex mu;
     std::map<std::tuple<int32_t, const void *, const void *, const void *, const void *, const void *, const void *,
                         const void *, const void *, const void *, void *, int32_t>,
@@ -60,22 +65,36 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
     m.err = err;
     m.scratch = x->scratch;
     m.batch = batch;
-    const unsigned nb = (unsigned)((batch + 255) / 256);
+    // bucketing: at most 256 workgroups of 1024 threads, grid-stride over the shots
+    const unsigned nb = (unsigned)std::min<int64_t>(256, (batch + kBucketThreads - 1) / kBucketThreads);
     hipLaunchKernelGGL(k_mix_clear, dim3(1), dim3(64), 0, st, m);
-    hipLaunchKernelGGL(k_mix_count, dim3(nb), dim3(256), 0, st, m);
-    hipLaunchKernelGGL(k_mix_scatter, dim3(nb), dim3(256), 0, st, m);
-    // one persistent grid per (pattern, lift size) present, largest L first
+    hipLaunchKernelGGL(k_mix_count, dim3(nb), dim3(kBucketThreads), 0, st, m);
+    hipLaunchKernelGGL(k_mix_plan, dim3(1), dim3(64), 0, st, m);
+    hipLaunchKernelGGL(k_mix_scatter, dim3(nb), dim3(kBucketThreads), 0, st, m);
+    // one persistent grid per (pattern, lift size) present, largest L first;
+    // the L = 128 grids on the side stream, overlapping the others
     const unsigned w64 = (unsigned)waves, w128 = (unsigned)x->waves128;
     const bool *g = x->has_grid;
     const dim3 hb(64 * kMixBlockWaves);
-    if (g[3]) hipLaunchKernelGGL((k_mix_block<ShapeLP35Z>), dim3(w128), hb, 0, st, m);
-    if (g[7]) hipLaunchKernelGGL((k_mix_block<ShapeLP35X>), dim3(w128), hb, 0, st, m);
+    const bool fork = (g[3] || g[7]) && (g[0] || g[1] || g[2] || g[4] || g[5] || g[6]);
+    hipStream_t bs = st;
+    hipError_t fe = hipSuccess;
+    if (fork) {
+        fe = hipEventRecord(x->ev_fork, st);
+        if (fe == hipSuccess) fe = hipStreamWaitEvent(x->side, x->ev_fork, 0);
+        if (fe != hipSuccess) return hip_error(fe, "mixed_decode: fork");
+        bs = x->side;
+    }
+    if (g[3]) hipLaunchKernelGGL((k_mix_block<ShapeLP35Z>), dim3(w128), hb, 0, bs, m);
+    if (g[7]) hipLaunchKernelGGL((k_mix_block<ShapeLP35X>), dim3(w128), hb, 0, bs, m);
+    if (fork && (fe = hipEventRecord(x->ev_join, x->side)) != hipSuccess) return hip_error(fe, "mixed_decode: join");
     if (g[2]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 64>), dim3(w64), dim3(64), 0, st, m);
     if (g[6]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 64>), dim3(w64), dim3(64), 0, st, m);
     if (g[1]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 32>), dim3(w64), dim3(64), 0, st, m);
     if (g[5]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 32>), dim3(w64), dim3(64), 0, st, m);
     if (g[0]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 16>), dim3(w64), dim3(64), 0, st, m);
     if (g[4]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 16>), dim3(w64), dim3(64), 0, st, m);
+    if (fork && (fe = hipStreamWaitEvent(st, x->ev_join, 0)) != hipSuccess) return hip_error(fe, "mixed_decode: join");
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "mixed_decode: launch");
     return QLDPC_OK;
@@ -120,10 +139,16 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
     }
     hipError_t e = hipSetDevice(x->device);
     if (e == hipSuccess) e = hipMalloc(&x->scratch, sizeof(int32_t) * (mix::kScratchHead + (size_t)max_batch));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&x->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&x->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (x->scratch) (void)hipFree(x->scratch);
+        if (x->side) (void)hipStreamDestroy(x->side);
+        if (x->ev_fork) (void)hipEventDestroy(x->ev_fork);
+        if (x->ev_join) (void)hipEventDestroy(x->ev_join);
         delete x;
-        return set_error(QLDPC_ERR_OUT_OF_MEMORY, "mixed_create: scratch allocation");
+        return set_error(QLDPC_ERR_OUT_OF_MEMORY, "mixed_create: scratch, stream or event allocation");
     }
     *out = x;
     return QLDPC_OK;
@@ -132,7 +157,11 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
 qldpc_status qldpc_mixed_destroy(qldpc_mixed x) {
     if (!x) return QLDPC_OK;
     for (auto &kv : x->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (x->side) (void)hipStreamSynchronize(x->side);
     if (x->scratch) (void)hipFree(x->scratch);
+    if (x->side) (void)hipStreamDestroy(x->side);
+    if (x->ev_fork) (void)hipEventDestroy(x->ev_fork);
+    if (x->ev_join) (void)hipEventDestroy(x->ev_join);
     delete x;
     return QLDPC_OK;
 }

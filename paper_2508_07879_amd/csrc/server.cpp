@@ -7,8 +7,10 @@
 // slots -- device buffers, pinned staging, a stream and a mixed-code plan
 // each -- whose number is set by the HBM budget.  Whenever a slot is free it
 // admits queued requests (FIFO, up to the slot's shot capacity) as one
-// micro-batch: copy-in, one mixed-code persistent decode for the plain
-// min-sum shots, one neural decode per code for the neural shots, copy-out,
+// micro-batch: one copy-in of the packed inputs; for the plain min-sum shots
+// one single-code decode per code (small micro-batches) or one mixed-code
+// persistent decode (large ones with several codes); one neural decode per
+// code for the neural shots; one copy-out of the packed outputs; an
 // event.  Micro-batches on different slots overlap on the device.  Finished
 // slots scatter their results into the requests' host buffers and post
 // completions.  Every shot's result is that of decoding it alone.
@@ -55,15 +57,15 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     qldpc_mixed plan = nullptr;
-    int32_t *d_cid = nullptr, *h_cid = nullptr;
-    int64_t *d_soff = nullptr, *h_soff = nullptr, *d_eoff = nullptr, *h_eoff = nullptr;
-    uint32_t *d_syn = nullptr, *h_syn = nullptr, *d_err = nullptr, *h_err = nullptr;
-    float *d_prior = nullptr, *h_prior = nullptr;
-    uint8_t *d_conv = nullptr, *h_conv = nullptr, *d_iters = nullptr, *h_iters = nullptr, *d_used = nullptr;
+    // One input and one output block per slot, packed per micro-batch so
+    // that a micro-batch moves with one copy each way (see launch_slot).
+    unsigned char *d_in = nullptr, *h_in = nullptr, *d_out = nullptr, *h_out = nullptr;
+    uint8_t *d_used = nullptr;
+    size_t o_conv = 0, o_iters = 0;       // output offsets of the launched micro-batch
+    std::vector<int64_t> eoff;            // per shot: error-word offset in the output block
     std::vector<Request> reqs;
     bool busy = false;
     int32_t shots = 0;
-    int64_t syn_words = 0, err_words = 0;
 };
 
 }  // namespace
@@ -74,6 +76,12 @@ struct qldpc_server_s {
     std::vector<const float *> weights;
     int32_t max_sw = 0, max_ew = 0;
     std::vector<Slot> slots;
+    // Light-load lane: one mapped-I/O session per code (null where none
+    // could be made).  When nothing is in flight and the queue holds a single
+    // small plain request, it is decoded at once through its code's session:
+    // one launch reading and writing pinned host memory, no copies and no
+    // micro-batch packing.
+    std::vector<qldpc_session> fast;
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Request> pending;
@@ -100,90 +108,132 @@ hipError_t host_alloc(T **p, size_t n) { return hipHostMalloc((void **)p, n * si
 
 void free_slot(Slot &s) {
     if (s.plan) qldpc_mixed_destroy(s.plan);
-    for (void *d : {(void *)s.d_cid, (void *)s.d_soff, (void *)s.d_eoff, (void *)s.d_syn, (void *)s.d_err,
-                    (void *)s.d_prior, (void *)s.d_conv, (void *)s.d_iters, (void *)s.d_used})
+    for (void *d : {(void *)s.d_in, (void *)s.d_out, (void *)s.d_used})
         if (d) (void)hipFree(d);
-    for (void *h : {(void *)s.h_cid, (void *)s.h_soff, (void *)s.h_eoff, (void *)s.h_syn, (void *)s.h_err,
-                    (void *)s.h_prior, (void *)s.h_conv, (void *)s.h_iters})
+    for (void *h : {(void *)s.h_in, (void *)s.h_out})
         if (h) (void)hipHostFree(h);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.stream) (void)hipStreamDestroy(s.stream);
     s = Slot{};
 }
 
+// Capacities of a slot's packed blocks for `shots` shots: inputs = priors,
+// then the mixed-plan index arrays (code id, syndrome and error offsets),
+// then the syndrome words; outputs = error words, flags, iterations.
+size_t slot_in_bytes(int64_t shots, int32_t sw) { return (size_t)shots * (4 + 4 + 8 + 8 + 4 * (size_t)sw) + 16; }
+size_t slot_out_bytes(int64_t shots, int32_t ew) { return (size_t)shots * (4 * (size_t)ew + 2) + 16; }
+
 // Device bytes one slot holds for `shots` shots.
 size_t slot_device_bytes(int64_t shots, int32_t sw, int32_t ew) {
-    return (size_t)shots * (4 + 8 + 8 + 4 * (size_t)sw + 4 * (size_t)ew + 4 + 1 + 1 + 1) + 4 * ((size_t)shots + 17);
+    return slot_in_bytes(shots, sw) + slot_out_bytes(shots, ew) + (size_t)shots + 4 * ((size_t)shots + 17);
 }
 
-// Packs the slot's requests into its staging and launches the micro-batch.
+inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
+
+// Micro-batches of at most this many plain min-sum shots decode with one
+// single-code launch per code present; larger ones through the mixed-code
+// persistent plan (three bucketing kernels and a persistent grid per lift
+// size, which pay off only on large batches).
+constexpr int32_t kDirectShots = 1024;
+
+// Largest request the light-load lane takes (its sessions' capacity).
+constexpr int32_t kFastShots = 64;
+
+// Packs the slot's requests into its staging and launches the micro-batch:
+// one host-to-device copy of the packed inputs, the decodes, one
+// device-to-host copy of the packed outputs, an event.  Shots are ordered
+// plain min-sum first, then neural, each grouped by code, so every code's
+// shots of one decoder are contiguous.
 qldpc_status launch_slot(qldpc_server srv, Slot &s) {
     if (++srv->launches == srv->fail_launch_at)
         return set_error(QLDPC_ERR_DEVICE, "server: injected launch failure");
     const int32_t nc = (int32_t)srv->codes.size();
-    // plain min-sum shots first (ragged, any code), then neural shots per code
-    int32_t shot = 0;
+    struct Group { int32_t first = -1, count = 0; int64_t sw0 = 0, ew0 = 0; };
+    std::vector<Group> plain(nc), neural(nc);
+    int32_t n = 0, n_plain = 0, plain_codes = 0;
     int64_t sw_at = 0, ew_at = 0;
-    std::vector<int32_t> nms_first(nc, -1), nms_count(nc, 0);
-    std::vector<int64_t> nms_sw(nc, 0), nms_ew(nc, 0);
-    auto place = [&](Request &r) {
-        const qldpc_code c = srv->codes[r.code];
-        const int32_t sw = (c->m + 31) / 32, ew = (c->n + 31) / 32;
-        r.first_shot = shot;
-        for (int32_t i = 0; i < r.nshots; ++i) {
-            s.h_cid[shot] = r.code;
-            s.h_soff[shot] = sw_at;
-            s.h_eoff[shot] = ew_at;
-            std::memcpy(s.h_syn + sw_at, r.syn + (size_t)i * sw, sizeof(uint32_t) * sw);
-            s.h_prior[shot] = r.prior[i];
-            sw_at += sw;
-            ew_at += ew;
-            ++shot;
-        }
-    };
-    for (Request &r : s.reqs)
-        if (r.decoder == 0) place(r);
-    const int32_t n_plain = shot;
-    for (int32_t c = 0; c < nc; ++c) {
-        for (Request &r : s.reqs)
-            if (r.decoder == 1 && r.code == c) {
-                if (nms_first[c] < 0) {
-                    nms_first[c] = shot;
-                    nms_sw[c] = sw_at;
-                    nms_ew[c] = ew_at;
+    for (int32_t dcd = 0; dcd < 2; ++dcd)
+        for (int32_t c = 0; c < nc; ++c)
+            for (Request &r : s.reqs)
+                if (r.decoder == dcd && r.code == c) {
+                    Group &g = dcd == 0 ? plain[c] : neural[c];
+                    if (g.first < 0) {
+                        g.first = n;
+                        g.sw0 = sw_at;
+                        g.ew0 = ew_at;
+                        if (dcd == 0) ++plain_codes;
+                    }
+                    const qldpc_code cc = srv->codes[c];
+                    r.first_shot = n;
+                    g.count += r.nshots;
+                    n += r.nshots;
+                    if (dcd == 0) n_plain += r.nshots;
+                    sw_at += (int64_t)r.nshots * ((cc->m + 31) / 32);
+                    ew_at += (int64_t)r.nshots * ((cc->n + 31) / 32);
                 }
-                nms_count[c] += r.nshots;
-                place(r);
+    const bool mixed = n_plain > kDirectShots && plain_codes > 1;
+    const int32_t n_idx = mixed ? n_plain : 0;
+    const size_t o_prior = 0, o_cid = o_prior + 4 * (size_t)n, o_soff = align8(o_cid + 4 * (size_t)n_idx),
+                 o_eoff = o_soff + 8 * (size_t)n_idx, o_syn = o_eoff + 8 * (size_t)n_idx,
+                 in_bytes = o_syn + 4 * (size_t)sw_at;
+    float *h_prior = reinterpret_cast<float *>(s.h_in + o_prior);
+    int32_t *h_cid = reinterpret_cast<int32_t *>(s.h_in + o_cid);
+    int64_t *h_soff = reinterpret_cast<int64_t *>(s.h_in + o_soff);
+    int64_t *h_eoff = reinterpret_cast<int64_t *>(s.h_in + o_eoff);
+    uint32_t *h_syn = reinterpret_cast<uint32_t *>(s.h_in + o_syn);
+    s.eoff.resize(n);
+    for (Request &r : s.reqs) {
+        const qldpc_code cc = srv->codes[r.code];
+        const int32_t sw = (cc->m + 31) / 32, ew = (cc->n + 31) / 32;
+        const Group &g = r.decoder == 0 ? plain[r.code] : neural[r.code];
+        const int32_t k0 = r.first_shot - g.first;   // position inside its group
+        for (int32_t i = 0; i < r.nshots; ++i) {
+            const int32_t sh = r.first_shot + i;
+            const int64_t so = g.sw0 + (int64_t)(k0 + i) * sw, eo = g.ew0 + (int64_t)(k0 + i) * ew;
+            std::memcpy(h_syn + so, r.syn + (size_t)i * sw, sizeof(uint32_t) * sw);
+            h_prior[sh] = r.prior[i];
+            s.eoff[sh] = eo;
+            if (mixed && r.decoder == 0) {
+                h_cid[sh] = r.code;
+                h_soff[sh] = so;
+                h_eoff[sh] = eo;
             }
+        }
     }
-    s.shots = shot;
-    s.syn_words = sw_at;
-    s.err_words = ew_at;
+    s.shots = n;
+    s.o_conv = 4 * (size_t)ew_at;
+    s.o_iters = s.o_conv + (size_t)n;
+    const size_t out_bytes = s.o_iters + (size_t)n;
+    const float *d_prior = reinterpret_cast<const float *>(s.d_in + o_prior);
+    const uint32_t *d_syn = reinterpret_cast<const uint32_t *>(s.d_in + o_syn);
+    uint32_t *d_err = reinterpret_cast<uint32_t *>(s.d_out);
+    uint8_t *d_conv = s.d_out + s.o_conv, *d_iters = s.d_out + s.o_iters;
     hipStream_t st = s.stream;
-    hipError_t e = hipSuccess;
-    if (n_plain > 0) {
-        e = hipMemcpyAsync(s.d_cid, s.h_cid, sizeof(int32_t) * n_plain, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.d_soff, s.h_soff, sizeof(int64_t) * n_plain, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.d_eoff, s.h_eoff, sizeof(int64_t) * n_plain, hipMemcpyHostToDevice, st);
-    }
-    if (e == hipSuccess) e = hipMemcpyAsync(s.d_syn, s.h_syn, sizeof(uint32_t) * sw_at, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.d_prior, s.h_prior, sizeof(float) * shot, hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(s.d_in, s.h_in, in_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_error(e, "server: copy-in");
     qldpc_status rc = QLDPC_OK;
-    if (n_plain > 0)
-        rc = qldpc_mixed_decode(s.plan, n_plain, s.d_cid, s.d_soff, s.d_eoff, s.d_syn, s.d_prior, s.d_err, s.d_conv,
-                                s.d_iters, st);
+    if (mixed) {
+        rc = qldpc_mixed_decode(s.plan, n_plain, reinterpret_cast<const int32_t *>(s.d_in + o_cid),
+                                reinterpret_cast<const int64_t *>(s.d_in + o_soff),
+                                reinterpret_cast<const int64_t *>(s.d_in + o_eoff), d_syn, d_prior, d_err, d_conv,
+                                d_iters, st);
+    } else {
+        for (int32_t c = 0; c < nc && rc == QLDPC_OK; ++c) {
+            const Group &g = plain[c];
+            if (g.count == 0) continue;
+            rc = qldpc_decode_batch(srv->codes[c], &srv->cfg.params, g.count, d_syn + g.sw0, d_prior + g.first,
+                                    d_err + g.ew0, d_conv + g.first, d_iters + g.first, nullptr, st);
+        }
+    }
     for (int32_t c = 0; c < nc && rc == QLDPC_OK; ++c) {
-        if (nms_count[c] == 0) continue;
-        const int32_t f = nms_first[c];
-        rc = qldpc_nbp_decode(srv->codes[c], nms_count[c], srv->cfg.nms_T, srv->weights[c], &srv->cfg.params,
-                              s.d_syn + nms_sw[c], s.d_prior + f, s.d_err + nms_ew[c], s.d_conv + f,
-                              s.d_iters + f, s.d_used + f, st);
+        const Group &g = neural[c];
+        if (g.count == 0) continue;
+        rc = qldpc_nbp_decode(srv->codes[c], g.count, srv->cfg.nms_T, srv->weights[c], &srv->cfg.params,
+                              d_syn + g.sw0, d_prior + g.first, d_err + g.ew0, d_conv + g.first,
+                              d_iters + g.first, s.d_used + g.first, st);
     }
     if (rc != QLDPC_OK) return rc;
-    e = hipMemcpyAsync(s.h_err, s.d_err, sizeof(uint32_t) * ew_at, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.h_conv, s.d_conv, shot, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.h_iters, s.d_iters, shot, hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(s.h_out, s.d_out, out_bytes, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipEventRecord(s.done, st);
     if (e != hipSuccess) return hip_error(e, "server: copy-out");
     return QLDPC_OK;
@@ -212,11 +262,12 @@ void finish_slot(qldpc_server srv, Slot &s, qldpc_status status) {
         if (status == QLDPC_OK) {
             const qldpc_code c = srv->codes[r.code];
             const int32_t ew = (c->n + 31) / 32;
+            const uint32_t *h_err = reinterpret_cast<const uint32_t *>(s.h_out);
             for (int32_t i = 0; i < r.nshots; ++i) {
                 const int32_t sh = r.first_shot + i;
-                if (r.err) std::memcpy(r.err + (size_t)i * ew, s.h_err + s.h_eoff[sh], sizeof(uint32_t) * ew);
-                if (r.conv) r.conv[i] = s.h_conv[sh];
-                if (r.iters) r.iters[i] = s.h_iters[sh];
+                if (r.err) std::memcpy(r.err + (size_t)i * ew, h_err + s.eoff[sh], sizeof(uint32_t) * ew);
+                if (r.conv) r.conv[i] = s.h_out[s.o_conv + sh];
+                if (r.iters) r.iters[i] = s.h_out[s.o_iters + sh];
             }
         }
         done.push_back(completion_of(r, status, t));
@@ -260,6 +311,37 @@ void worker_loop(qldpc_server srv) {
                 (void)hipStreamSynchronize(s.stream);
                 finish_slot(srv, s, QLDPC_ERR_DEVICE);
                 progressed = true;
+            }
+        }
+        // light load: nothing in flight and one small plain request queued
+        bool idle = true;
+        for (Slot &s : srv->slots) idle = idle && !s.busy;
+        if (idle && !srv->stop) {
+            Request r{};
+            bool have = false;
+            {
+                std::lock_guard<std::mutex> g(srv->mu);
+                if (srv->pending.size() == 1) {
+                    const Request &f = srv->pending.front();
+                    if (f.decoder == 0 && f.nshots <= kFastShots && srv->fast[f.code]) {
+                        r = f;
+                        srv->pending.pop_front();
+                        have = true;
+                    }
+                }
+            }
+            if (have) {
+                srv->inflight_shots += r.nshots;
+                qldpc_status rc = QLDPC_OK;
+                if (++srv->launches == srv->fail_launch_at)
+                    rc = set_error(QLDPC_ERR_DEVICE, "server: injected launch failure");
+                else
+                    rc = qldpc_session_decode(srv->fast[r.code], r.nshots, r.syn, r.prior, r.err, r.conv, r.iters);
+                srv->inflight_shots -= r.nshots;
+                if (rc != QLDPC_OK) fail_server(srv, rc, qldpc_last_error());
+                std::lock_guard<std::mutex> g(srv->mu);
+                srv->completions.push_back(completion_of(r, rc, now_ns()));
+                continue;
             }
         }
         // admit queued requests into free slots
@@ -354,26 +436,14 @@ qldpc_status qldpc_server_create(const qldpc_server_config *cfg, qldpc_server *o
     srv->slots.resize(nslots);
     qldpc_status rc = QLDPC_OK;
     for (Slot &s : srv->slots) {
-        const size_t sw = (size_t)B * srv->max_sw, ew = (size_t)B * srv->max_ew;
+        const size_t ib = slot_in_bytes(B, srv->max_sw), ob = slot_out_bytes(B, srv->max_ew);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = dev_alloc(&s.d_cid, B);
-        if (e == hipSuccess) e = dev_alloc(&s.d_soff, B);
-        if (e == hipSuccess) e = dev_alloc(&s.d_eoff, B);
-        if (e == hipSuccess) e = dev_alloc(&s.d_syn, sw);
-        if (e == hipSuccess) e = dev_alloc(&s.d_err, ew);
-        if (e == hipSuccess) e = dev_alloc(&s.d_prior, B);
-        if (e == hipSuccess) e = dev_alloc(&s.d_conv, B);
-        if (e == hipSuccess) e = dev_alloc(&s.d_iters, B);
+        if (e == hipSuccess) e = dev_alloc(&s.d_in, ib);
+        if (e == hipSuccess) e = dev_alloc(&s.d_out, ob);
         if (e == hipSuccess) e = dev_alloc(&s.d_used, B);
-        if (e == hipSuccess) e = host_alloc(&s.h_cid, B);
-        if (e == hipSuccess) e = host_alloc(&s.h_soff, B);
-        if (e == hipSuccess) e = host_alloc(&s.h_eoff, B);
-        if (e == hipSuccess) e = host_alloc(&s.h_syn, sw);
-        if (e == hipSuccess) e = host_alloc(&s.h_err, ew);
-        if (e == hipSuccess) e = host_alloc(&s.h_prior, B);
-        if (e == hipSuccess) e = host_alloc(&s.h_conv, B);
-        if (e == hipSuccess) e = host_alloc(&s.h_iters, B);
+        if (e == hipSuccess) e = host_alloc(&s.h_in, ib);
+        if (e == hipSuccess) e = host_alloc(&s.h_out, ob);
         if (e != hipSuccess) break;
         rc = qldpc_mixed_create(cfg->codes, cfg->ncodes, &cfg->params, (int32_t)B, 0, &s.plan);
         if (rc != QLDPC_OK) break;
@@ -383,6 +453,10 @@ qldpc_status qldpc_server_create(const qldpc_server_config *cfg, qldpc_server *o
         delete srv;
         return e != hipSuccess ? set_error(QLDPC_ERR_OUT_OF_MEMORY, "server_create: slot allocation") : rc;
     }
+    srv->fast.assign(cfg->ncodes, nullptr);
+    for (int c = 0; c < cfg->ncodes; ++c)
+        if (qldpc_session_create(cfg->codes[c], &cfg->params, kFastShots, QLDPC_IO_MAPPED, &srv->fast[c]) != QLDPC_OK)
+            srv->fast[c] = nullptr;   // that code's small requests go through micro-batches
     srv->worker = std::thread(worker_loop, srv);
     *out = srv;
     return QLDPC_OK;
@@ -442,6 +516,8 @@ qldpc_status qldpc_server_destroy(qldpc_server srv) {
     srv->cv.notify_all();
     if (srv->worker.joinable()) srv->worker.join();
     for (Slot &s : srv->slots) free_slot(s);
+    for (qldpc_session f : srv->fast)
+        if (f) (void)qldpc_session_destroy(f);
     delete srv;
     return QLDPC_OK;
 }

@@ -184,3 +184,50 @@ def test_inference_with_continuing_fallback(L, p, neg):
     with pytest.raises(abi.QldpcError) as ei:          # max_iters below T
         abi.qldpc_nbp_decode_continue(dec.handle, b.B, T, to_dev(w), T - 1, 0.75, syn, pr, err, conv, it, used)
     assert ei.value.status == abi.QLDPC_ERR_INVALID_ARG
+
+
+def test_training_shape_T16_B4096():
+    """The training configuration itself (L = 64, T = 16, 4096 shots, a 2 GB
+    saved trajectory): the forward pass on sampled shots equals the oracle's
+    posteriors of all 16 iterations; the batch gradient equals the sum of the
+    gradients of its 64-shot chunks (each a forward and backward of its own),
+    so the reduction over the large batch drops and doubles nothing; one chunk
+    of 8 shots equals the FP64 oracle adjoint."""
+    c, H, dec = code(64)
+    B, T, CH = 4096, 16, 64
+    b = noise.Batch(c.hz, 46, np.arange(B), 0.05)
+    w = weights(9, T, c.hz.nnz, 0.5, 1.0, 0.001)
+    G = np.random.default_rng(47).normal(size=(T, B, c.n)).astype(np.float32)
+    syn, wt, ws, post = forward(dec, b, w)
+    gw = torch.empty_like(wt)
+    abi.qldpc_nbp_backward(dec.handle, B, T, wt, syn, ws, to_dev(G), gw)
+    torch.cuda.synchronize()
+    g_all = gw.cpu().numpy().astype(np.float64)
+    pick = np.array([0, 1, 777, 2048, 3000, B - 2, B - 1])
+    o = oracle.flood_f32(H, b.s[pick], b.gamma[pick], weights=w, max_iters=T, early_stop=False, want_Q_all=True)
+    got = post.cpu().numpy()[:, pick, :]
+    assert np.all(np.abs(got - o.Q_all) <= 1e-5 * np.maximum(np.abs(o.Q_all), np.abs(b.gamma[pick])[None, :, None]))
+    del post, ws
+    g_sum = np.zeros_like(g_all)
+    g_abs = np.zeros_like(g_all)
+    for lo in range(0, B, CH):
+        bc = noise.Batch(c.hz, 46, np.arange(lo, lo + CH), 0.05)
+        s_c, w_c, ws_c, _ = forward(dec, bc, w)
+        gc = torch.empty_like(w_c)
+        abi.qldpc_nbp_backward(dec.handle, CH, T, w_c, s_c, ws_c, to_dev(np.ascontiguousarray(G[:, lo:lo + CH])), gc)
+        torch.cuda.synchronize()
+        gcn = gc.cpu().numpy().astype(np.float64)
+        g_sum += gcn
+        g_abs += np.abs(gcn)
+    assert np.all(np.abs(g_all - g_sum) <= 1e-4 * g_abs + 1e-5), float(np.abs(g_all - g_sum).max())
+    # 8 shots against the FP64 oracle adjoint at T = 16
+    b8 = noise.Batch(c.hz, 46, np.arange(8), 0.05)
+    s8, w8, ws8, _ = forward(dec, b8, w)
+    g8 = torch.empty_like(w8)
+    G8 = np.ascontiguousarray(G[:, :8])
+    abi.qldpc_nbp_backward(dec.handle, 8, T, w8, s8, ws8, to_dev(G8), g8)
+    torch.cuda.synchronize()
+    of = oracle.flood_f32(H, b8.s, b8.gamma, weights=w, max_iters=T, early_stop=False, want_q_traj=True)
+    go, ga = oracle.nms_adjoint_f64(H, b8.s, w.astype(np.float64), of.q_traj.astype(np.float64),
+                                    G8.astype(np.float64))
+    assert np.all(np.abs(g8.cpu().numpy() - go) <= 1e-4 * ga + 1e-6)
