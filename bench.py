@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--nms-eval-shots", type=int, default=1 << 18)
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of open-loop load per offered rate of the serving sweep (0 = skip)")
+    ap.add_argument("--lift128-shots", type=int, default=32768,
+                    help="shots of the L = 128 register-layout row (0 = skip)")
     ap.add_argument("--seed", type=int, default=20250807)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run one plain device copy of MIB MiB (a known-size "
@@ -146,8 +148,8 @@ def main():
 
     # ---------------- headline: FP32 flooding --------------------------------
     # the register-resident layout (messages in VGPRs) is the fastest for
-    # FP32 flooding at L <= 64; the LDS layout is reported among the variants
-    head_layout = abi.QLDPC_LAYOUT_WAVE_REG if args.L <= 64 else abi.QLDPC_LAYOUT_WAVE
+    # FP32 flooding at L <= 128; the LDS layout is reported among the variants
+    head_layout = abi.QLDPC_LAYOUT_WAVE_REG if args.L <= 128 else abi.QLDPC_LAYOUT_WAVE
     wall, kms, its = measure(abi.QLDPC_F32, abi.QLDPC_FLOOD, args.steps, args.warmup, layout=head_layout)
     syn_per_step = B * len(P_LIST)
     value = syn_per_step * args.steps / wall
@@ -217,10 +219,11 @@ def main():
     variants = {}
     if not args.no_variants:
         W, RG = abi.QLDPC_LAYOUT_WAVE, abi.QLDPC_LAYOUT_WAVE_REG
-        R_ = RG if args.L <= 64 else W
-        for name, fmt, sched, bpm, lay in (("f32_flood_lds_layout", 0, 0, 4, W), ("int8_flood", 1, 0, 1, R_),
+        R_ = RG if args.L <= 64 else W          # layered
+        RF = RG if args.L <= 128 else W         # flooding
+        for name, fmt, sched, bpm, lay in (("f32_flood_lds_layout", 0, 0, 4, W), ("int8_flood", 1, 0, 1, RF),
                                            ("f32_layered", 0, 1, 4, R_), ("f32_layered_lds_layout", 0, 1, 4, W),
-                                           ("int8_layered", 1, 1, 1, R_), ("int16_flood", 2, 0, 2, R_),
+                                           ("int8_layered", 1, 1, 1, R_), ("int16_flood", 2, 0, 2, RF),
                                            ("int16_layered", 2, 1, 2, R_), ("int16_flood_lds_layout", 2, 0, 2, W),
                                            ("int8_flood_lds_layout", 1, 0, 1, W)):
             w, k_, it_ = measure(fmt, sched, max(3, args.steps // 4), 1, layout=lay)
@@ -318,6 +321,47 @@ def main():
                 edge_model_frac=edge_h / (ms_h * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 hbm_traffic_bytes_per_launch=recorded_traffic(None, traffic_file))
             del ws
+
+    # ---------------- L = 128: two register wavefronts per shot ----------------
+    # each wavefront holds half of every circulant's rows in VGPRs and the
+    # variable pass exchanges through LDS; against 8-wave workgroups with the
+    # messages in LDS, on the same inputs (outputs compared bit for bit)
+    lift128 = None
+    if args.lift128_shots > 0 and args.L != 128:
+        L2, B2 = 128, args.lift128_shots
+        c2 = lp.lp_code(L2)
+        d2 = Decoder(c2.hz, device=0)
+        b2 = noise.Batch(c2.hz, args.seed + 128, np.arange(B2), 0.03)
+        syn2 = torch.from_numpy(bits.pack_bits(b2.s).view(np.int32)).to(dev)
+        pri2 = {abi.QLDPC_F32: torch.from_numpy(b2.gamma).to(dev),
+                abi.QLDPC_I8Q4: torch.from_numpy(b2.gamma_q4()).to(dev),
+                abi.QLDPC_I16Q8: torch.from_numpy(b2.gamma_q8()).to(dev)}
+        ops2 = alu_ops_per_shot_iter(c2.hz)
+        lift128 = dict(code=f"LP 3x5, L={L2} (N={c2.hz.n}, E={c2.hz.nnz})", shots=B2, p=0.03,
+                       schedule="flooding", max_iters=32, alu_ops_per_shot_iter=ops2, formats={})
+        for fname, fmt in (("f32", abi.QLDPC_F32), ("int16", abi.QLDPC_I16Q8), ("int8", abi.QLDPC_I8Q4)):
+            row, outs = {}, {}
+            for lname, lay, nw in (("register_2wave", abi.QLDPC_LAYOUT_WAVE_REG, 0),
+                                   ("block_8wave_lds", abi.QLDPC_LAYOUT_BLOCK, 8)):
+                prm = d2.params(fmt=fmt, layout=lay, waves_per_shot=nw)
+                o2 = d2.outputs(B2)
+                abi.qldpc_decode_batch(d2.handle, prm, B2, syn2, pri2[fmt], *o2[:3], None, stream)
+                torch.cuda.synchronize()
+                e0l, e1l = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0l.record(stream)
+                for _ in range(5):
+                    abi.qldpc_decode_batch(d2.handle, prm, B2, syn2, pri2[fmt], *o2[:3], None, stream)
+                e1l.record(stream)
+                torch.cuda.synchronize()
+                ms2 = e0l.elapsed_time(e1l) / 5
+                it2 = int(o2[2].to(torch.int64).sum().item())
+                row[lname] = dict(value=B2 / (ms2 * 1e-3), unit="syndromes/s", ms_per_launch=ms2,
+                                  mean_iters=it2 / B2,
+                                  alu_frac=it2 * ops2 / (ms2 * 1e-3) / (VALU_PEAK_TOPS * 1e12))
+                outs[lname] = [x.cpu() for x in o2[:3]]
+            row["identical_outputs"] = all(torch.equal(x, y) for x, y in
+                                           zip(outs["register_2wave"], outs["block_8wave_lds"]))
+            lift128["formats"][fname] = row
 
     # ---------------- latency: one syndrome per request, host to host ---------
     latency = None
@@ -529,6 +573,7 @@ def main():
         "serving": serving,
         "mixed_batch": mixed,
         "large_lift_hbm": hbm,
+        "lift_128_register": lift128,
         "pcie_inclusive": pcie,
         "cpu_baseline": cpu,
         "cpu_oracle_detail": cpu_detail,

@@ -141,16 +141,15 @@ typedef enum {
 typedef enum {
     QLDPC_LAYOUT_AUTO = 0,   /* tuned choice for (code, format, batch) when
                                 qldpc_autotune recorded one; otherwise:
-                                L >= 256 HBM; flooding at L = 128, or at
-                                L = 64 with batch < 512, BLOCK (16 waves
-                                below 512 shots, else 8); otherwise
-                                WAVE_REG for L <= 64, WAVE for L = 128     */
+                                L >= 256 HBM; flooding at L >= 64 with
+                                batch < 512 BLOCK (16 waves); otherwise
+                                WAVE_REG for L <= 64 and for flooding at
+                                L = 128, WAVE for layered at L = 128       */
     QLDPC_LAYOUT_WAVE = 1,   /* one wavefront decodes one shot (or 64 / L
                                 shots when L < 64); throughput layout        */
     QLDPC_LAYOUT_BLOCK = 2,  /* one workgroup of several wavefronts decodes
                                 one shot, messages in LDS; flooding, L >= 64;
-                                the latency layout, and AUTO's throughput
-                                layout at L = 128 (8 wavefronts)            */
+                                the latency layout                          */
     QLDPC_LAYOUT_HBM = 4,    /* one workgroup decodes one shot with its edge
                                 messages in a caller-provided device
                                 workspace (qldpc_decode_batch_ws): codes too
@@ -160,8 +159,12 @@ typedef enum {
     QLDPC_LAYOUT_WAVE_REG = 3 /* as WAVE, with every message (and, layered,
                                 every a-posteriori value) kept in the lanes'
                                 registers and moved between lanes by
-                                cross-lane permutes instead of LDS (int8
-                                messages as 32-bit integers); L <= 64 only
+                                cross-lane permutes instead of LDS (integer
+                                messages as exact values on FP32 lanes);
+                                L <= 64, and L = 128 with flooding: one
+                                workgroup of two wavefronts per shot, each
+                                holding half of every circulant's rows, the
+                                variable pass exchanging through LDS
                                 (otherwise QLDPC_ERR_UNSUPPORTED)            */
 } qldpc_layout;
 

@@ -37,7 +37,7 @@ FLAGS = [
 # values.  Measured on MI355X: 56.5 -> 53.2 us for a 32-iteration resident
 # decode at L = 64.
 _NO_IEEE = ["-fno-honor-nans", "-mno-amdgpu-ieee"]
-FILE_FLAGS = {"wreg_": _NO_IEEE, "mixed": _NO_IEEE, "block": _NO_IEEE, "resident": _NO_IEEE}
+FILE_FLAGS = {"wreg_": _NO_IEEE, "wreg2_": _NO_IEEE, "mixed": _NO_IEEE, "block": _NO_IEEE, "resident": _NO_IEEE}
 
 
 def _file_flags(src: str) -> list:

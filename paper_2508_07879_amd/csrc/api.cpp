@@ -115,15 +115,15 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
             }
         }
         // Defaults measured on MI355X (65536 shots at L = 64, 32768 at L = 128,
-        // p = 0.01 / 0.03 / 0.05): at L <= 64 messages in registers (FP32
-        // flooding 32.0 M syndromes/s against 26.9 M for 8-wave workgroups); at
-        // L = 128 flooding an 8-wave workgroup per shot with messages in LDS
-        // (7.8 M FP32, 7.75 M int8, against 3.3 / 4.55 M with messages in HBM
-        // and 2.3 / 7.0 M for a wavefront per shot); small batches (latency)
-        // 16-wave workgroups.
-        const bool reg_ok = code->L <= 64;
+        // p = 0.01 / 0.03 / 0.05): messages in registers (L = 64 FP32 flooding
+        // 37.2 M syndromes/s against 26.9 M for 8-wave workgroups; L = 128
+        // flooding, two wavefronts per shot, 12.3 M FP32 / 11.8 M int8 against
+        // 8.4 / 7.7 M for 8-wave workgroups with messages in LDS and 3.3 /
+        // 4.55 M with messages in HBM); L = 128 layered a wavefront per shot;
+        // small batches (latency) 16-wave workgroups.
+        const bool reg_ok = code->L <= 64 || (code->L == 128 && p->sched == QLDPC_FLOOD);
         if (!found) {
-            if (block_ok && (batch < 512 || code->L == 128)) {
+            if (block_ok && batch < 512) {
                 layout = QLDPC_LAYOUT_BLOCK;
                 if (nw == 0) nw = batch < 512 ? 16 : 8;
             } else {
@@ -136,8 +136,9 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
             return fail(QLDPC_ERR_UNSUPPORTED, "decode: the workgroup layout needs flooding and L >= 64");
         if (nw == 0) nw = 16;
     }
-    if (layout == QLDPC_LAYOUT_WAVE_REG && code->L > 64)
-        return fail(QLDPC_ERR_UNSUPPORTED, "decode: register-resident messages need L <= 64");
+    if (layout == QLDPC_LAYOUT_WAVE_REG && (code->L > 128 || (code->L == 128 && p->sched != QLDPC_FLOOD)))
+        return fail(QLDPC_ERR_UNSUPPORTED, "decode: register-resident messages need L <= 64, or L = 128 with "
+                                           "flooding (two wavefronts per shot)");
     if (layout == QLDPC_LAYOUT_HBM && (p->sched != QLDPC_FLOOD || code->L < 128))
         return fail(QLDPC_ERR_UNSUPPORTED, "decode: the HBM layout needs flooding and L in {128, 256, 512}");
     if (layout != QLDPC_LAYOUT_HBM && code->L > 128)
@@ -482,7 +483,8 @@ qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, 
     if (code->L > 128) return fail(QLDPC_ERR_UNSUPPORTED, "autotune: lifts above 128 have one layout (HBM messages)");
     struct Cand { int layout, nw; };
     std::vector<Cand> cands = {{QLDPC_LAYOUT_WAVE, 0}};
-    if (code->L > 0 && code->L <= 64) cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});
+    if (code->L > 0 && (code->L <= 64 || (code->L == 128 && params->sched == QLDPC_FLOOD)))
+        cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});
     if (params->sched == QLDPC_FLOOD && code->L >= 64) {
         cands.push_back({QLDPC_LAYOUT_BLOCK, 8});
         cands.push_back({QLDPC_LAYOUT_BLOCK, 16});

@@ -42,7 +42,7 @@ def test_css_condition_and_shapes():
 
 @pytest.mark.parametrize("L,layout,fmt", [(16, REG, 0), (32, REG, 0), (64, REG, 0), (16, WAVE, 1), (64, WAVE, 0),
                                           (64, WAVE, 1), (128, WAVE, 0), (128, WAVE, 1), (64, BLOCK, 0),
-                                          (64, BLOCK, 1), (128, BLOCK, 0)])
+                                          (64, BLOCK, 1), (128, BLOCK, 0), (128, REG, 0), (128, REG, 1)])
 def test_hx_side_matches_oracle(L, layout, fmt):
     c, sd, H, dec = side(L, 1)
     b = noise.Batch(sd, 61 + L + fmt, np.arange(150 if L < 128 else 60), 0.05)

@@ -189,18 +189,20 @@ def test_resident_session_rejects_unsupported_configs():
 
 @pytest.mark.parametrize("fmt", [0, 1])
 def test_auto_layout_at_L128_large_batch(fmt):
-    """AUTO at L = 128 with a large batch takes 8-wave workgroups with messages
-    in LDS and asks for no workspace; a sample of the batch equals the oracle
-    and the explicit workgroup layout bit for bit."""
+    """AUTO at L = 128 flooding with a large batch takes the two-wavefront
+    register layout and asks for no workspace; it equals that layout and the
+    8-wave workgroup layout bit for bit, and a sample of the batch equals the
+    oracle."""
     c, H, dec = code(128)
     B = 600
     b = noise.Batch(c.hz, 77 + fmt, np.arange(B), 0.05)
     prior = b.gamma if fmt == 0 else b.gamma_q4()
     assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(fmt=fmt), B) == 0
     g_auto = gpu_decode(dec, b.s, prior, fmt=fmt, layout=abi.QLDPC_LAYOUT_AUTO)
+    g_reg = gpu_decode(dec, b.s, prior, fmt=fmt, layout=abi.QLDPC_LAYOUT_WAVE_REG)
     g_blk = gpu_decode(dec, b.s, prior, fmt=fmt, layout=abi.QLDPC_LAYOUT_BLOCK, waves_per_shot=8)
-    for x, y in zip(g_auto, g_blk):
-        assert np.array_equal(x, y)
+    for x, y, z in zip(g_auto, g_reg, g_blk):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
     idx = np.arange(0, B, 7)
     o = oracle_decode(H, b.s[idx], prior[idx], fmt=fmt)
     sub = tuple(x[idx] for x in g_auto)

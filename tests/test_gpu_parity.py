@@ -193,8 +193,58 @@ def test_register_resident_int8_bit_exact(L, sched):
     run_case(L, 60, 0.05, fmt=1, sched=sched, max_iters=5, early_stop=False, seed=39, layout=REG)
 
 
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("per_bit", [False, True])
+def test_register_resident_L128(fmt, per_bit):
+    """L = 128 with messages in registers: one workgroup of two wavefronts per
+    shot, each holding half of every circulant's rows, the variable pass and
+    the syndrome test exchanging through LDS.  Same decisions, flags,
+    iterations and posteriors as the oracle (FP32 within 1e-5, integer
+    formats bit-exact)."""
+    run_case(128, 96, 0.05, fmt=fmt, per_bit=per_bit, seed=57, layout=REG)
+    run_case(128, 64, 0.02, fmt=fmt, per_bit=per_bit, seed=58, layout=REG)
+
+
+def test_register_resident_L128_edge_cases():
+    run_case(128, 40, 0.05, max_iters=10, early_stop=False, seed=59, layout=REG)
+    g, _ = run_case(128, 17, 0.05, max_iters=1, seed=60, layout=REG)
+    assert np.all(g[2] == 1)
+    run_case(128, 33, 0.04, alpha=1.0, seed=61, layout=REG)
+    run_case(128, 21, 0.03, alpha=0.5, seed=62, layout=REG)
+    c, H, dec = code(128)
+    g, _ = run_case(128, 3, 0.03, syn=np.zeros((3, c.hz.m), np.uint8), seed=63, layout=REG)
+    assert np.all(g[1] == 1) and np.all(g[2] == 1)
+    # the H_X block pattern
+    dx = Decoder(c.hx)
+    b = noise.Batch(c.hx, 64, np.arange(80), 0.05)
+    gx = gpu_decode(dx, b.s, b.gamma, layout=REG)
+    ox = oracle_decode(c.hx.dense(), b.s, b.gamma)
+    assert_parity(gx, ox, b.gamma[:, None], 0, tag="L=128 H_X register layout")
+
+
+def test_register_resident_L128_large_batch_sampled():
+    """32768 shots at p = 0.05 in one launch: converged shots reproduce their
+    syndromes, a sample matches the oracle shot by shot, and every shot
+    equals the 8-wave workgroup layout's decode."""
+    c, H, dec = code(128)
+    B = 32768
+    b = noise.Batch(c.hz, 1100, np.arange(B), 0.05)
+    g = gpu_decode(dec, b.s, b.gamma, posterior=False, layout=REG)
+    gb = gpu_decode(dec, b.s, b.gamma, posterior=False, layout=abi.QLDPC_LAYOUT_BLOCK, waves_per_shot=8)
+    for x, y in zip(g[:3], gb[:3]):
+        assert np.array_equal(x, y)
+    e, conv, it, _ = g
+    ok = conv == 1
+    assert ok.mean() > 0.5
+    assert np.array_equal(noise.syndromes(c.hz, e[ok]), b.s[ok])
+    idx = np.unique(np.concatenate([np.arange(0, B, 2048), [B - 1], np.nonzero(~ok)[0][:8]]))
+    o = oracle_decode(H, b.s[idx], b.gamma[idx])
+    assert np.array_equal(e[idx], o.e) and np.array_equal(conv[idx], o.converged)
+    assert np.array_equal(it[idx], o.iters)
+
+
 def test_register_resident_rejects_unsupported():
-    for L, fmt, sched in ((128, 0, 0), (128, 0, 1), (128, 1, 0)):
+    for L, fmt, sched in ((128, 0, 1), (128, 1, 1), (256, 0, 0)):
         c, H, dec = code(L)
         p = dec.params(fmt=fmt, sched=sched, layout=REG)
         err, conv, it, _ = dec.outputs(2)
