@@ -358,8 +358,10 @@ typedef struct qldpc_mixed_s *qldpc_mixed;
  * max_batch shots (FP32 flooding, per-shot priors; params gives alpha,
  * iterations and early stop; lifts 16, 32, 64 and 128).  Allocates
  * 4 * (max_batch + 24) bytes of device scratch.  One persistent grid per
- * (pattern, lift size) decodes its shots: messages in registers for L <= 64,
- * in the LDS of 8-wave workgroups (two per compute unit) for L = 128.  use_graph = 1: every distinct argument set is captured
+ * (pattern, lift size) decodes its shots with its messages in registers: a
+ * wavefront per tile of 64 / L shots for L <= 64, a workgroup of two
+ * wavefronts per shot for L = 128 (on a second stream, overlapping the
+ * others).  use_graph = 1: every distinct argument set is captured
  * once as a hipGraph (bucketing kernels + persistent decoders) and
  * replayed. */
 qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const qldpc_decode_params *params,
@@ -380,8 +382,9 @@ qldpc_status qldpc_mixed_decode(qldpc_mixed plan, int32_t batch, const int32_t *
                                 uint8_t *iters_used, void *stream);
 
 /* Sets the persistent grid sizes of a plan: `reg_waves` wavefronts for each
- * (pattern, lift) with L <= 64 and `block_workgroups` workgroups for L = 128
- * (0 keeps the current value; defaults 12 and 2 per compute unit).  With
+ * (pattern, lift) with L <= 64 and `block_workgroups` two-wave workgroups
+ * for L = 128 (0 keeps the current value; defaults 12 and 6 per compute
+ * unit).  With
  * fewer waves than tiles every wavefront claims several tiles in turn.  The
  * plan's captured graphs are dropped.  Errors: INVALID_ARG. */
 qldpc_status qldpc_mixed_set_grid(qldpc_mixed plan, int32_t reg_waves, int32_t block_workgroups);

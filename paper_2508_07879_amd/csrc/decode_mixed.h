@@ -8,19 +8,18 @@
 // wavefronts per (block pattern, lift size) then claims tiles of same-code
 // shots from its own atomic counter until none are left: for L <= 64 every
 // message stays in registers (one 64-lane group of 64 / L shots per tile),
-// for L = 128 in the LDS of a persistent workgroup of 8 waves running the
-// workgroup-per-shot decoder (one shot per tile).  Codes of both patterns (H_Z and
-// H_X of one CSS code, say) can share a batch, so both sides of a code are
+// for L = 128 in the registers of a persistent workgroup of two waves, each
+// holding half of every circulant's rows (one shot per tile).  Codes of both
+// patterns (H_Z and H_X of one CSS code, say) can share a batch, so both sides of a code are
 // decoded in one launch sequence.  Each shot's result depends only on its
 // own syndrome and prior, never on its tile mates or grid.
 #pragma once
-#include "decode_block.h"
 #include "decode_wave.h"
+#include "decode_wreg2.h"
 
 namespace qldpc {
 
 constexpr int kMaxMixCodes = 8;
-constexpr int kMixBlockWaves = 8;   // waves per workgroup of the L = 128 grid
 
 struct MixedArgs {
     DecodeArgs base;                       // alpha, iterations, priors, conv / iters outputs
@@ -210,29 +209,28 @@ void k_mix_decode(const MixedArgs m) {
     }
 }
 
-// Persistent decoder of the L = 128 shots: each 8-wave workgroup claims one
-// shot at a time and decodes it with its messages in LDS (61 KB FP32, two
-// workgroups per compute unit).  Every value that decides whether a wave
-// reaches a barrier is workgroup-uniform (broadcast through LDS, then
-// readfirstlane).
+// Persistent decoder of the L = 128 shots: each workgroup of two waves claims
+// one shot at a time and decodes it with its messages in registers (three
+// waves per SIMD, six workgroups per compute unit).  Every value that decides
+// whether a wave reaches a barrier is workgroup-uniform (broadcast through
+// LDS, then readfirstlane).
 template <class S>
-__global__ __launch_bounds__(64 * kMixBlockWaves) void k_mix_block(const MixedArgs m) {
-    constexpr int L = 128, NW = kMixBlockWaves;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[BlockLds<S, L, 0, NW>::bytes];
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_mix_wreg2(const MixedArgs m) {
+    __shared__ wreg2::Lds<S, 0> sh;
     __shared__ int tile;
     for (;;) {
-        if (threadIdx.x == 0) tile = atomicAdd(mix::tile_ctr(m, S::WHICH, L), 1);
+        if (threadIdx.x == 0) tile = atomicAdd(mix::tile_ctr(m, S::WHICH, wreg2::kL), 1);
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(tile);
-        __syncthreads();   // everyone has read tile before it is claimed again
+        __syncthreads();   // both waves have read tile before it is claimed again
         int c, first, cnt;
-        mix::locate(m, mix::grid_of(S::WHICH, L), 1, t, c, first, cnt);
+        mix::locate(m, mix::grid_of(S::WHICH, wreg2::kL), 1, t, c, first, cnt);
         if (c < 0) return;   // every L = 128 tile of this pattern is taken
         const long shot = (long)(int64_t)wave::uniform64((uint64_t)(int64_t)mix::order(m)[first]);
         const int64_t so = (int64_t)wave::uniform64((uint64_t)m.syn_off[shot]);
         const int64_t eo = (int64_t)wave::uniform64((uint64_t)m.err_off[shot]);
         const DevCode *code = (const DevCode *)wave::uniform64((uint64_t)mix::code_table(m)[c]);
-        block_decode<S, L, 0, NW, false, false>(m.base, code, shot, m.syn + so, m.err + eo, lds);
+        wreg2_decode<S, 0, false, false>(m.base, code, shot, m.syn + so, m.err + eo, sh);
         __syncthreads();   // LDS reused by the next shot
     }
 }

@@ -42,7 +42,7 @@ typedef __attribute__((address_space(3))) float lds_f32;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 constexpr int kL = 128;
-constexpr int kVB = 4;   // block columns per LDS exchange batch
+constexpr int kVB = 8;   // block columns per LDS exchange batch (2, 4, 8, 12: 12.53, 12.79, 12.89, 12.91 M syndromes/s)
 
 // Edge slots of the columns of batch B: their count and, per column, the
 // index of its first slot inside the batch.
@@ -87,35 +87,33 @@ struct Lds {
 
 }  // namespace wreg2
 
-// One workgroup of two waves per shot; grid = batch.
+// Decodes one shot with the two waves of the calling workgroup (both waves
+// must call it with the same, workgroup-uniform arguments): `syn` and `err`
+// point at the shot's syndrome and error words, priors, flags and the
+// a-posteriori output are indexed by `shot`.  Leaves with both waves at the
+// same iteration; the caller fences LDS before reusing `sh`.
 template <class S, int FMT, bool PER_BIT, bool POST>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
-void k_wreg2(const DecodeArgs a) {
+__device__ __forceinline__ void wreg2_decode(const DecodeArgs &a, const DevCode *code, const long shot,
+                                             const uint32_t *syn, uint32_t *err_shot, wreg2::Lds<S, FMT> &sh) {
     using namespace wave;
     using B = wreg2::BatchesOf<S>;
     using prior_t = typename Fmt<FMT>::prior_t;
     constexpr int L = wreg2::kL, MB = S::MB, NB = S::NB, DC = S::DC, N = NB * L;
-    constexpr int SW = MB * L / 32, EW = NB * L / 32;
     constexpr int NBATCH = B::V.NBATCH;
-    __shared__ wreg2::Lds<S, FMT> sh;
 
-    const long shot = xcd_wave_index(blockIdx.x, gridDim.x);
-    if (shot >= a.batch) return;                                   // workgroup-uniform
-    if (a.only && a.only[shot] == 0) return;                       // workgroup-uniform
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = threadIdx.x & 63;
     const uint32_t r = (uint32_t)(64 * w + t);                     // this lane's circulant row
     const uint32_t r4 = r << 2;
-    const CodePtr cpb0 = const_code(a.code);
+    const CodePtr cpb0 = const_code(code);
     CodePtr cpb = cpb0;
     auto reload_table = [&]() {
-        uint64_t v = (uint64_t)a.code;
+        uint64_t v = (uint64_t)code;
         asm volatile("" : "+s"(v));
         cpb = (CodePtr)v;
     };
 
     // syndrome bits of this lane's checks: bit R = s of check R * L + r
-    const uint32_t *syn = a.syn + shot * SW;
     uint32_t sb = 0;
 #pragma unroll
     for (int R = 0; R < MB; ++R) {
@@ -267,7 +265,7 @@ void k_wreg2(const DecodeArgs a) {
             // this wave's half of every column: words 4 C + 2 w, 4 C + 2 w + 1
             // (a rolled loop from an opaque base: unrolled, the compiler would
             // hoist 34 output addresses out of the iteration loop)
-            uint64_t eo = uniform64((uint64_t)(a.err + shot * EW + 2 * w));
+            uint64_t eo = uniform64((uint64_t)(err_shot + 2 * w));
             asm volatile("" : "+s"(eo));
             uint32_t *err = (uint32_t *)eo;
 #pragma unroll 1
@@ -289,6 +287,20 @@ void k_wreg2(const DecodeArgs a) {
             return;
         }
     }
+}
+
+// One workgroup of two waves per shot; grid = batch.  Per-bit priors and the
+// a-posteriori output need more live registers than 168 (three waves per SIMD)
+// leave without spilling, so those variants run two waves per SIMD.
+template <class S, int FMT, bool PER_BIT, bool POST>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu((!PER_BIT && !POST) ? 3 : 2)))
+void k_wreg2(const DecodeArgs a) {
+    constexpr int SW = S::MB * wreg2::kL / 32, EW = S::NB * wreg2::kL / 32;
+    __shared__ wreg2::Lds<S, FMT> sh;
+    const long shot = xcd_wave_index(blockIdx.x, gridDim.x);
+    if (shot >= a.batch) return;                                   // workgroup-uniform
+    if (a.only && a.only[shot] == 0) return;                       // workgroup-uniform
+    wreg2_decode<S, FMT, PER_BIT, POST>(a, a.code, shot, a.syn + shot * SW, a.err + shot * EW, sh);
 }
 
 template <class S, int FMT>

@@ -17,10 +17,10 @@ struct qldpc_mixed_s {
     qldpc_code codes[kMaxMixCodes] = {};
     qldpc_decode_params params{};
     int32_t waves = 0;              // persistent grid size for each lift L <= 64 (registers)
-    int32_t waves128 = 0;           // workgroups of the L = 128 grid (messages in LDS)
+    int32_t waves128 = 0;           // two-wave workgroups of the L = 128 grid
     bool has_grid[mix::kMixGrids] = {};   // (pattern, L) pairs among the plan's codes
     int32_t *scratch = nullptr;     // device
-    // The L = 128 workgroup grids run on a second stream, forked from and
+    // The L = 128 grids run on a second stream, forked from and
     // joined back into the caller's (or the capture) stream, so that they
     // overlap the register grids instead of running before them.
     hipStream_t side = nullptr;
@@ -75,7 +75,7 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
     // the L = 128 grids on the side stream, overlapping the others
     const unsigned w64 = (unsigned)waves, w128 = (unsigned)x->waves128;
     const bool *g = x->has_grid;
-    const dim3 hb(64 * kMixBlockWaves);
+    const dim3 hb(128);
     const bool fork = (g[3] || g[7]) && (g[0] || g[1] || g[2] || g[4] || g[5] || g[6]);
     hipStream_t bs = st;
     hipError_t fe = hipSuccess;
@@ -85,8 +85,8 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
         if (fe != hipSuccess) return hip_error(fe, "mixed_decode: fork");
         bs = x->side;
     }
-    if (g[3]) hipLaunchKernelGGL((k_mix_block<ShapeLP35Z>), dim3(w128), hb, 0, bs, m);
-    if (g[7]) hipLaunchKernelGGL((k_mix_block<ShapeLP35X>), dim3(w128), hb, 0, bs, m);
+    if (g[3]) hipLaunchKernelGGL((k_mix_wreg2<ShapeLP35Z>), dim3(w128), hb, 0, bs, m);
+    if (g[7]) hipLaunchKernelGGL((k_mix_wreg2<ShapeLP35X>), dim3(w128), hb, 0, bs, m);
     if (fork && (fe = hipEventRecord(x->ev_join, x->side)) != hipSuccess) return hip_error(fe, "mixed_decode: join");
     if (g[2]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 64>), dim3(w64), dim3(64), 0, st, m);
     if (g[6]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 64>), dim3(w64), dim3(64), 0, st, m);
@@ -128,7 +128,7 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
     x->waves = 12 * cus;     // register grids: up to three waves per SIMD
-    x->waves128 = 2 * cus;   // L = 128: two 8-wave workgroups per CU (61 KB of LDS each)
+    x->waves128 = 6 * cus;   // L = 128: six two-wave workgroups per CU (three waves per SIMD)
     for (int c = 0; c < ncodes; ++c) {
         const int L = codes[c]->L;
         if (L != 16 && L != 32 && L != 64 && L != 128) {

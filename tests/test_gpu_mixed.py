@@ -185,7 +185,7 @@ def oracle_sample(st, mb, out, split, per_code=24):
 
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_persistent_grids_claim_many_tiles(use_graph):
-    """37 register wavefronts per lift and 11 workgroups for L = 128 over
+    """37 register wavefronts per lift and 11 two-wave workgroups for L = 128 over
     6000 shots: every wavefront and workgroup decodes many tiles in turn."""
     st = setup()
     mb = MixedBatch(st["codes"], 55, 6000)
@@ -201,7 +201,7 @@ def test_persistent_grids_claim_many_tiles(use_graph):
 
 def test_full_size_mixed_batch():
     """The benchmark's 262144-shot mixed batch at the default grid sizes
-    (3072 register wavefronts per lift, 512 workgroups for L = 128, so tiles
+    (3072 register wavefronts per lift, 1536 two-wave workgroups for L = 128, so tiles
     outnumber waves for every lift): every shot against its single-code
     decode, a sample against the oracle."""
     st = setup()
@@ -209,7 +209,7 @@ def test_full_size_mixed_batch():
     for c, L in enumerate(LS):
         n = int((mb.cid == c).sum())
         tiles = -(-n // (64 // L)) if L <= 64 else n
-        assert tiles > (3072 if L <= 64 else 512), (L, n)
+        assert tiles > (3072 if L <= 64 else 1536), (L, n)
     (out,) = run_mixed(st, mb, True)
     split = single_code_all(st, mb, out)
     oracle_sample(st, mb, out, split, per_code=16)
