@@ -428,6 +428,24 @@ def main():
             finally:
                 abi.qldpc_session_destroy(sess)
         latency["both_css_sides"] = both
+        # the L = 128 code (N = 4352): one syndrome per request, resident decoder
+        c128 = lp.lp_code(128)
+        d128 = Decoder(c128.hz, device=0)
+        b128 = noise.Batch(c128.hz, args.seed + 1280, np.arange(pool), 0.05)
+        syn128 = np.ascontiguousarray(bits.pack_bits(b128.s))
+        lift128_lat = {}
+        for early in (False, True):
+            prm = d128.params(max_iters=32, early_stop=early, layout=abi.QLDPC_LAYOUT_BLOCK)
+            sess = abi.qldpc_session_create(d128.handle, prm, 1, abi.QLDPC_IO_RESIDENT)
+            try:
+                abi.qldpc_session_latency(sess, 500, 1, pool, syn128, b128.gamma)      # warm-up
+                lat = abi.qldpc_session_latency(sess, max(1, args.latency_reqs // 5), 1, pool, syn128, b128.gamma)
+                key = "early_stop_p0.05" if early else "all_32_iterations"
+                lift128_lat[key] = lat_stats(lat)
+                print(json.dumps({"latency": "L128", "case": key, **lift128_lat[key]}), file=sys.stderr, flush=True)
+            finally:
+                abi.qldpc_session_destroy(sess)
+        latency["lift_128"] = lift128_lat
         latency["definition"] = ("one syndrome per request, from host memory to the decision in host memory, "
                                  "steady-clock per request; FP32 flooding, workgroup-per-shot layout (16 waves). "
                                  "early_stop and all_32_iterations: resident decoder woken through a doorbell in "
@@ -436,7 +454,8 @@ def main():
                                  "synchronisation per request, same buffers; batch_64_early_stop: 64 syndromes "
                                  "per request (p = 0.01), one workgroup per syndrome; both_css_sides: one "
                                  "request = the H_Z syndrome of X errors and the H_X syndrome of independent Z "
-                                 "errors at the same rate, decoded together by one resident grid")
+                                 "errors at the same rate, decoded together by one resident grid; lift_128: the "
+                                 "L = 128 code (N = 4352), resident decoder, 32 iterations and early stop at p = 0.05")
 
     # ---------------- neural min-sum: trained in-run, judged by plain min-sum ----
     neural = None

@@ -13,12 +13,13 @@
 //
 // Per iteration k:
 //   A: check pass of iteration k; each block row also tests the decisions of
-//      iteration k-1 (s_R xor rot(e_C, a) over its blocks, 64-bit ballots in
-//      LDS) and raises a flag on a violated check;
+//      iteration k-1 (its rows' parity words against the syndrome, see
+//      kBlockParityWords) and raises a flag on a violated check;
 //   barrier; every wave reads the flag: all checks satisfied -> emit the
 //      outputs of iteration k-1 and stop (the check pass just run only
 //      overwrote messages, not e or Q);
-//   B: variable pass, a posteriori, decisions (ballots to LDS);
+//   B: variable pass, a posteriori, decisions (ballots to LDS, changes XORed
+//      into the parity words);
 //   barrier.
 // After the last iteration one more test pass decides the convergence flag.
 // Two barriers per iteration; flags are double buffered by iteration parity.
@@ -74,8 +75,18 @@ struct BlockLds {
     static constexpr size_t e_off = (msg_bytes + 15) & ~size_t(15);   // uint64 [NB][PPL]
     static constexpr size_t f_off = e_off + (size_t)S::NB * PPL * 8;  // uint32 flags[2]
     static constexpr size_t s_off = f_off + 16;                          // uint32 syndrome words
-    static constexpr size_t bytes = s_off + (((size_t)S::MB * L + 31) / 32) * 4;
+    static constexpr size_t a_off = (s_off + (((size_t)S::MB * L + 31) / 32) * 4 + 15) & ~size_t(15);
+    static constexpr size_t bytes = a_off + (size_t)L * 4;               // uint32 check-row parity [L]
 };
+
+// Syndrome test by check-row parity words: the variable pass XORs every
+// change of a decision into the word of each check row the variable meets
+// (bit R for block row R, an LDS atomic per edge, skipped for an item where
+// no decision of the wave changed), so after iteration k word row holds bit R
+// = the parity of check (R, row) under the decisions of iteration k.  The
+// check pass of iteration k + 1 compares its own rows' words with the
+// syndrome: a read and three VALU per item instead of d rotated ballots.
+constexpr bool kBlockParityWords = true;
 
 // Decodes shot `shot` of the code whose shift table is `code_table` (its
 // syndrome words at syn, error words to err; priors, flags and posteriors
@@ -98,10 +109,13 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const DevCode 
     constexpr int CN_ITEMS = MB * PPL, VN_ITEMS = NB * PPL;
     using Plan = VnPlanOf<S, L, NW>;
     constexpr int VN_PER_WAVE = Plan::P.per_wave;
+    static_assert(VN_PER_WAVE <= 32, "one bit per variable item of a wave");
 
     msg_t *msg = reinterpret_cast<msg_t *>(lds);
     uint64_t *emask = reinterpret_cast<uint64_t *>(lds + Lay::e_off);
     uint32_t *flag = reinterpret_cast<uint32_t *>(lds + Lay::f_off);
+    uint32_t *rowpar = reinterpret_cast<uint32_t *>(lds + Lay::a_off);
+    constexpr bool XT = kBlockParityWords;
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -146,6 +160,10 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const DevCode 
         flag[0] = 0;
         flag[1] = 0;
     }
+    if constexpr (XT) {
+        for (int i = threadIdx.x; i < L; i += 64 * NW) rowpar[i] = 0;   // decisions of iteration 0: all 0
+    }
+    uint32_t eprev = 0;   // bit slot: this lane's decision of VN item slot in the last iteration
     acc_t Qr[POST ? VN_PER_WAVE : 1];
     __syncthreads();
 
@@ -187,9 +205,21 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const DevCode 
         }
     };
 
-    // syndrome test of the decisions in emask; raises flag[par] on a violation
+    // syndrome test of the last decisions; raises flag[par] on a violation
     auto test_rows = [&](auto Wc, int par) {
         constexpr int W = decltype(Wc)::value;
+        if constexpr (XT) {
+            bool bad = false;
+            static_for<0, CN_ITEMS>([&](auto Ic) {
+                constexpr int it = decltype(Ic)::value;
+                if constexpr (it % NW == W) {
+                    constexpr int R = it / PPL, h = it % PPL;
+                    bad |= (((rowpar[lane + 64 * h] ^ sb[h]) >> R) & 1u) != 0;
+                }
+            });
+            if (ballot(bad) != 0 && lane == 0) atomicOr(&flag[par], 1u);
+            return;
+        }
         static_for<0, CN_ITEMS>([&](auto Ic) {
             constexpr int it = decltype(Ic)::value;
             if constexpr (it % NW == W) {
@@ -257,11 +287,12 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const DevCode 
                     constexpr int C = it / PPL, h = it % PPL;
                     constexpr int d = S::T.col_deg[C];
                     acc_t r[d];
-                    int idx[d];
+                    int idx[d], row[d];
                     static_for<0, d>([&](auto Jc) {
                         constexpr int i = decltype(Jc)::value;
                         constexpr int slot = S::T.col_R[C][i] * DC + S::T.col_j[C][i];
-                        idx[i] = slot * L + vn_index<L>(lane, h, (uint32_t)code->shift[slot]);
+                        row[i] = vn_index<L>(lane, h, (uint32_t)code->shift[slot]);
+                        idx[i] = slot * L + row[i];
                         r[i] = (acc_t)msg[idx[i]];
                     });
                     acc_t Q;
@@ -287,8 +318,26 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const DevCode 
                         Q = sum;
                     }
                     if constexpr (POST) Qr[Plan::P.slot[it]] = Q;
-                    const uint64_t m = ballot(Q < (acc_t)0);
+                    const bool e = Q < (acc_t)0;
+                    const uint64_t m = ballot(e);
                     if (lane == 0) emask[C * PPL + h] = m;
+                    // without early stop only the last iteration's decisions are
+                    // tested: eprev stays 0 until then, so that iteration XORs the
+                    // whole decision vector into the (still zero) parity words
+                    if constexpr (XT) {
+                        constexpr int sl = Plan::P.slot[it];
+                        const bool chg = e != (((eprev >> sl) & 1u) != 0);
+                        if ((a.early_stop || k == a.max_iters) && ballot(chg) != 0) {   // wave-uniform
+                            const uint32_t cw = chg ? 1u : 0u;
+                            static_for<0, d>([&](auto Jc) {
+                                constexpr int i = decltype(Jc)::value;
+                                constexpr int R = S::T.col_R[C][i];
+                                __hip_atomic_fetch_xor(&rowpar[row[i]], cw << R, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                            });
+                            eprev ^= cw << sl;
+                        }
+                    }
                 }
             });
             if (threadIdx.x == 0) flag[(k + 1) & 1] = 0;
