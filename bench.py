@@ -271,10 +271,11 @@ def main():
         finally:
             abi.qldpc_mixed_destroy(plan)
 
-    # ---------------- large lift: edge messages in HBM --------------------------
-    # L = 256 messages do not fit on chip: they sit in a device workspace and
-    # every iteration streams them through HBM, so the message format sets the
-    # bytes moved (4, 2 or 1 per message; Table 1's reduced-precision formats).
+    # ---------------- large lift: edge messages in HBM or in registers ---------
+    # L = 256 with its messages in a device workspace: every iteration streams
+    # them through HBM, so the message format sets the bytes moved (4, 2 or 1
+    # per message; Table 1's reduced-precision formats).  Beside it the layout
+    # AUTO takes there: four register wavefronts per shot, messages on chip.
     hbm = None
     if args.hbm_shots > 0:
         Lh, Bh = 256, args.hbm_shots
@@ -289,7 +290,8 @@ def main():
                     abi.QLDPC_I16Q8: torch.from_numpy(bh.gamma_q8()).to(dev)}
         io_h = (ch.hz.m + 31) // 32 * 4 + 4 + (ch.hz.n + 31) // 32 * 4 + 2
         hbm = dict(code=f"LP 3x5, L={Lh} (N={ch.hz.n}, E={ch.hz.nnz})", shots=Bh, p=0.03,
-                   layout="workgroup per shot (8 waves), edge messages in an HBM workspace",
+                   layout="workgroup per shot (8 waves), edge messages in an HBM workspace; register_layout: "
+                          "a workgroup of four wavefronts per shot, messages in registers",
                    input_generation_s=gen_h, formats={})
         for fname, fmt, bpm, traffic_file in (("f32", abi.QLDPC_F32, 4, "traffic_k_hbm_f32_L256.json"),
                                               ("int16", abi.QLDPC_I16Q8, 2, "traffic_k_hbm_i16_L256.json"),
@@ -321,6 +323,21 @@ def main():
                 edge_model_frac=edge_h / (ms_h * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 hbm_traffic_bytes_per_launch=recorded_traffic(None, traffic_file))
             del ws
+            # the same shots with the messages in registers (AUTO's layout here)
+            prm_r = dh.params(fmt=fmt, layout=abi.QLDPC_LAYOUT_WAVE_REG)
+            outr = dh.outputs(Bh)
+            abi.qldpc_decode_batch(dh.handle, prm_r, Bh, syn_h, pr_h, *outr[:3], None, stream)
+            torch.cuda.synchronize()
+            e0h.record(stream)
+            for _ in range(3):
+                abi.qldpc_decode_batch(dh.handle, prm_r, Bh, syn_h, pr_h, *outr[:3], None, stream)
+            e1h.record(stream)
+            torch.cuda.synchronize()
+            ms_r = e0h.elapsed_time(e1h) / 3
+            hbm["formats"][fname]["register_layout"] = dict(
+                value=Bh / (ms_r * 1e-3), unit="syndromes/s", ms_per_launch=ms_r,
+                alu_frac=its_h * alu_ops_per_shot_iter(ch.hz) / (ms_r * 1e-3) / (VALU_PEAK_TOPS * 1e12),
+                identical_outputs=all(torch.equal(x, y) for x, y in zip(outh[:3], outr[:3])))
 
     # ---------------- L = 128: two register wavefronts per shot ----------------
     # each wavefront holds half of every circulant's rows in VGPRs and the

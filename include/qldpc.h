@@ -141,10 +141,11 @@ typedef enum {
 typedef enum {
     QLDPC_LAYOUT_AUTO = 0,   /* tuned choice for (code, format, batch) when
                                 qldpc_autotune recorded one; otherwise:
-                                L >= 256 HBM; flooding at L >= 64 with
-                                batch < 512 BLOCK (16 waves); otherwise
-                                WAVE_REG for L <= 64 and for flooding at
-                                L = 128, WAVE for layered at L = 128       */
+                                flooding at L in {64, 128} with batch < 512
+                                BLOCK (16 waves); otherwise WAVE_REG for
+                                L <= 64 and for flooding at L >= 128, WAVE
+                                for layered at L = 128, HBM (unsupported)
+                                for layered at L >= 256                    */
     QLDPC_LAYOUT_WAVE = 1,   /* one wavefront decodes one shot (or 64 / L
                                 shots when L < 64); throughput layout        */
     QLDPC_LAYOUT_BLOCK = 2,  /* one workgroup of several wavefronts decodes
@@ -152,20 +153,20 @@ typedef enum {
                                 the latency layout                          */
     QLDPC_LAYOUT_HBM = 4,    /* one workgroup decodes one shot with its edge
                                 messages in a caller-provided device
-                                workspace (qldpc_decode_batch_ws): codes too
-                                large for on-chip messages; flooding with
-                                L in {128, 256, 512}; AUTO picks it for
-                                L >= 256                                    */
+                                workspace (qldpc_decode_batch_ws); flooding
+                                with L in {128, 256, 512}; never AUTO's
+                                choice (the register layout is faster)      */
     QLDPC_LAYOUT_WAVE_REG = 3 /* as WAVE, with every message (and, layered,
                                 every a-posteriori value) kept in the lanes'
                                 registers and moved between lanes by
                                 cross-lane permutes instead of LDS (integer
                                 messages as exact values on FP32 lanes);
-                                L <= 64, and L = 128 with flooding: one
-                                workgroup of two wavefronts per shot, each
-                                holding half of every circulant's rows, the
-                                variable pass exchanging through LDS
-                                (otherwise QLDPC_ERR_UNSUPPORTED)            */
+                                L <= 64, and L in {128, 256, 512} with
+                                flooding: one workgroup of L / 64 wavefronts
+                                per shot, each holding 64 rows of every
+                                circulant, the variable pass exchanging
+                                through LDS (otherwise
+                                QLDPC_ERR_UNSUPPORTED)                       */
 } qldpc_layout;
 
 typedef struct {
@@ -205,7 +206,7 @@ qldpc_status qldpc_decode_batch(qldpc_code code, const qldpc_decode_params *para
 /* Device bytes of message workspace a decode of `batch` shots with these
  * parameters needs when called through qldpc_decode_batch_ws: batch * 120
  * * L * (4 for F32, 1 for I8Q4, 2 for I16Q8) when the chosen layout keeps messages in
- * device memory (QLDPC_LAYOUT_HBM; see its AUTO rule), else 0.  Errors as
+ * device memory (QLDPC_LAYOUT_HBM, asked for explicitly), else 0.  Errors as
  * qldpc_decode_batch. */
 qldpc_status qldpc_decode_workspace_bytes(qldpc_code code, const qldpc_decode_params *params, int32_t batch,
                                           size_t *bytes);
@@ -233,7 +234,7 @@ qldpc_status qldpc_decode_batch_ws(qldpc_code code, const qldpc_decode_params *p
  * messages on chip use no workspace.  A batch whose workspace
  * (qldpc_decode_workspace_bytes) exceeds the buffer returns
  * QLDPC_ERR_CAPACITY (e.g. at most 546 FP32 or 2184 int8 shots per call at
- * L = 256).  The first call on a device looks up that device's buffer
+ * L = 256 in the HBM layout).  The first call on a device looks up that device's buffer
  * (hipGetSymbolAddress) with the device current.  Every call on a device
  * shares its one buffer: calls that overlap on one device (other streams or
  * threads) race, and the caller must serialise them. */

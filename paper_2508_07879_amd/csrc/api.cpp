@@ -41,6 +41,15 @@ qldpc_status hip_error(hipError_t e, const char *what) {
 namespace {
 qldpc_status fail(qldpc_status st, const std::string &msg) { return set_error(st, msg); }
 qldpc_status hip_fail(hipError_t e, const char *what) { return hip_error(e, what); }
+
+// Messages in registers: a wavefront per 64 / L shots for L <= 64 (both
+// schedules), a workgroup of L / 64 wavefronts per shot for L = 128, 256,
+// 512 (flooding).
+bool reg_supported(const qldpc_code_s *code, int sched) {
+    if (code->L <= 0) return false;
+    if (code->L <= 64) return true;
+    return (code->L == 128 || code->L == 256 || code->L == 512) && sched == QLDPC_FLOOD;
+}
 }  // namespace
 
 namespace qldpc {
@@ -102,7 +111,12 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
     }
     const bool block_ok = p->sched == QLDPC_FLOOD && code->L >= 64;
     int layout = p->layout, nw = p->waves_per_shot;
-    if (layout == QLDPC_LAYOUT_AUTO && code->L > 128) layout = QLDPC_LAYOUT_HBM;   // messages do not fit on chip
+    // L = 256, 512: L / 64 register wavefronts per shot (FP32 flooding at L = 256,
+    // 8192 shots, p = 0.03: 3.9 M syndromes/s against 1.03 M with messages in
+    // HBM; L = 512, 4096 shots: 0.96 M against 0.35 M); layered decoding has
+    // neither layout there
+    if (layout == QLDPC_LAYOUT_AUTO && code->L > 128)
+        layout = p->sched == QLDPC_FLOOD ? QLDPC_LAYOUT_WAVE_REG : QLDPC_LAYOUT_HBM;
     if (layout == QLDPC_LAYOUT_AUTO) {
         bool found = false;
         {
@@ -121,7 +135,7 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
         // 8.4 / 7.7 M for 8-wave workgroups with messages in LDS and 3.3 /
         // 4.55 M with messages in HBM); L = 128 layered a wavefront per shot;
         // small batches (latency) 16-wave workgroups.
-        const bool reg_ok = code->L <= 64 || (code->L == 128 && p->sched == QLDPC_FLOOD);
+        const bool reg_ok = reg_supported(code, p->sched);
         if (!found) {
             if (block_ok && batch < 512) {
                 layout = QLDPC_LAYOUT_BLOCK;
@@ -136,13 +150,14 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
             return fail(QLDPC_ERR_UNSUPPORTED, "decode: the workgroup layout needs flooding and L >= 64");
         if (nw == 0) nw = 16;
     }
-    if (layout == QLDPC_LAYOUT_WAVE_REG && (code->L > 128 || (code->L == 128 && p->sched != QLDPC_FLOOD)))
-        return fail(QLDPC_ERR_UNSUPPORTED, "decode: register-resident messages need L <= 64, or L = 128 with "
-                                           "flooding (two wavefronts per shot)");
+    if (layout == QLDPC_LAYOUT_WAVE_REG && !reg_supported(code, p->sched))
+        return fail(QLDPC_ERR_UNSUPPORTED, "decode: register-resident messages need L <= 64, or flooding with "
+                                           "L in {128, 256, 512} (L / 64 wavefronts per shot)");
     if (layout == QLDPC_LAYOUT_HBM && (p->sched != QLDPC_FLOOD || code->L < 128))
         return fail(QLDPC_ERR_UNSUPPORTED, "decode: the HBM layout needs flooding and L in {128, 256, 512}");
-    if (layout != QLDPC_LAYOUT_HBM && code->L > 128)
-        return fail(QLDPC_ERR_UNSUPPORTED, "decode: lifts above 128 keep messages in HBM (QLDPC_LAYOUT_HBM)");
+    if (layout != QLDPC_LAYOUT_HBM && layout != QLDPC_LAYOUT_WAVE_REG && code->L > 128)
+        return fail(QLDPC_ERR_UNSUPPORTED, "decode: lifts above 128 keep messages in registers "
+                                           "(QLDPC_LAYOUT_WAVE_REG, flooding) or in HBM (QLDPC_LAYOUT_HBM)");
     key->layout = layout;
     key->nw = nw;
     return QLDPC_OK;
@@ -480,11 +495,12 @@ qldpc_status qldpc_autotune(qldpc_code code, const qldpc_decode_params *params, 
     if (!code || !params || !best) return fail(QLDPC_ERR_INVALID_ARG, "autotune: null argument");
     if (batch <= 0) return fail(QLDPC_ERR_INVALID_ARG, "autotune: batch must be positive");
     if (!syn || !priors || !err || !conv) return fail(QLDPC_ERR_INVALID_ARG, "autotune: null buffer");
-    if (code->L > 128) return fail(QLDPC_ERR_UNSUPPORTED, "autotune: lifts above 128 have one layout (HBM messages)");
+    if (code->L > 128)
+        return fail(QLDPC_ERR_UNSUPPORTED, "autotune: lifts above 128 have one layout without a workspace "
+                                           "(messages in registers, AUTO's choice)");
     struct Cand { int layout, nw; };
     std::vector<Cand> cands = {{QLDPC_LAYOUT_WAVE, 0}};
-    if (code->L > 0 && (code->L <= 64 || (code->L == 128 && params->sched == QLDPC_FLOOD)))
-        cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});
+    if (reg_supported(code, params->sched)) cands.push_back({QLDPC_LAYOUT_WAVE_REG, 0});
     if (params->sched == QLDPC_FLOOD && code->L >= 64) {
         cands.push_back({QLDPC_LAYOUT_BLOCK, 8});
         cands.push_back({QLDPC_LAYOUT_BLOCK, 16});
@@ -580,7 +596,7 @@ qldpc_status qldpc_tune_load(qldpc_code code, const char *path) {
         if (layout != QLDPC_LAYOUT_WAVE && layout != QLDPC_LAYOUT_BLOCK && layout != QLDPC_LAYOUT_WAVE_REG) continue;
         if (layout == QLDPC_LAYOUT_BLOCK && nw != 8 && nw != 16) continue;
         const int key = (int)nums[i];
-        if (layout == QLDPC_LAYOUT_WAVE_REG && code->L > 64) continue;
+        if (layout == QLDPC_LAYOUT_WAVE_REG && !reg_supported(code, (key / 16) % 2)) continue;   // key: tune_key
         code->tune[key] = TuneChoice{layout, nw, (float)nums[i + 3]};
     }
     return QLDPC_OK;

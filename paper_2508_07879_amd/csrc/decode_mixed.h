@@ -216,21 +216,21 @@ void k_mix_decode(const MixedArgs m) {
 // LDS, then readfirstlane).
 template <class S>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_mix_wreg2(const MixedArgs m) {
-    __shared__ wreg2::Lds<S, 0> sh;
+    __shared__ wreg2::Lds<S, 0, 128> sh;
     __shared__ int tile;
     for (;;) {
-        if (threadIdx.x == 0) tile = atomicAdd(mix::tile_ctr(m, S::WHICH, wreg2::kL), 1);
+        if (threadIdx.x == 0) tile = atomicAdd(mix::tile_ctr(m, S::WHICH, 128), 1);
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(tile);
         __syncthreads();   // both waves have read tile before it is claimed again
         int c, first, cnt;
-        mix::locate(m, mix::grid_of(S::WHICH, wreg2::kL), 1, t, c, first, cnt);
+        mix::locate(m, mix::grid_of(S::WHICH, 128), 1, t, c, first, cnt);
         if (c < 0) return;   // every L = 128 tile of this pattern is taken
         const long shot = (long)(int64_t)wave::uniform64((uint64_t)(int64_t)mix::order(m)[first]);
         const int64_t so = (int64_t)wave::uniform64((uint64_t)m.syn_off[shot]);
         const int64_t eo = (int64_t)wave::uniform64((uint64_t)m.err_off[shot]);
         const DevCode *code = (const DevCode *)wave::uniform64((uint64_t)mix::code_table(m)[c]);
-        wreg2_decode<S, 0, false, false>(m.base, code, shot, m.syn + so, m.err + eo, sh);
+        wreg2_decode<S, 0, false, false, 128>(m.base, code, shot, m.syn + so, m.err + eo, sh);
         __syncthreads();   // LDS reused by the next shot
     }
 }

@@ -1,15 +1,16 @@
-// Register-resident decoder for the lift size L = 128: one workgroup of two
-// wavefronts per shot, flooding schedule (Section 2, Algorithm 1).
+// Register-resident decoder for the lift sizes L = 128, 256, 512: one
+// workgroup of W = L / 64 wavefronts per shot, flooding schedule (Section 2,
+// Algorithm 1).
 //
-// Mapping.  Wave w, lane t owns row r = 64 w + t of every 128 x 128
-// circulant: check (R, r) of each block row, with the 8 messages of its
-// edges in registers (120 per lane, as in the L = 64 register decoder), and
-// variable (C, r) of each block column.  The check pass works on registers
-// only.  The variable pass needs the messages of checks (R, r - s mod 128),
-// which half the time live in the other wave, so it goes through LDS, a
-// batch of block columns at a time:
+// Mapping.  Wave w, lane t owns row r = 64 w + t of every L x L circulant:
+// check (R, r) of each block row, with the 8 messages of its edges in
+// registers (120 per lane, as in the L = 64 register decoder), and variable
+// (C, r) of each block column.  The check pass works on registers only.  The
+// variable pass needs the messages of checks (R, r - s mod L), which mostly
+// live in other waves, so it goes through LDS, a batch of block columns at a
+// time:
 //   1. every lane stores its messages of the batch's edge slots at its own
-//      row of a 128-entry slot row;
+//      row of an L-entry slot row;
 //   2. barrier; every lane reads the messages of its variable at rows
 //      r - s, forms the excluded sums in the oracle's order and writes each
 //      new message back to the row it came from (same address); it also
@@ -21,7 +22,7 @@
 // accesses are to consecutive rows or to the same rows rotated by the shift:
 // no bank conflicts.  After the last batch, the word of row r, XOR the
 // syndrome bits, is the syndrome test of the lane's 15 checks; the shot has
-// converged when neither wave found a violated check (flags in LDS, one more
+// converged when no wave found a violated check (flags in LDS, one more
 // barrier per iteration).
 //
 // Numerics are those of the other layouts: FP32 excluded sums left to right
@@ -41,26 +42,29 @@ typedef __attribute__((address_space(3))) unsigned char lds_u8;
 typedef __attribute__((address_space(3))) float lds_f32;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
-constexpr int kL = 128;
-constexpr int kVB = 8;   // block columns per LDS exchange batch (2, 4, 8, 12: 12.53, 12.79, 12.89, 12.91 M syndromes/s)
+// Block columns per LDS exchange batch.  L = 128, FP32, 3 x 32768 shots:
+// 2, 4, 8, 12 columns ran 12.53, 12.79, 12.89, 12.91 M syndromes/s.  At
+// L = 512 a batch of 4 keeps the exchange buffer at 30 KB.
+template <int L>
+constexpr int vb_of() { return L >= 512 ? 4 : 8; }
 
 // Edge slots of the columns of batch B: their count and, per column, the
 // index of its first slot inside the batch.
-template <class S>
+template <class S, int VB>
 struct Batches {
-    static constexpr int NBATCH = (S::NB + kVB - 1) / kVB;
+    static constexpr int NBATCH = (S::NB + VB - 1) / VB;
     int count[NBATCH];
     int first[S::NB];
     int max_count;
 };
 
-template <class S>
-constexpr Batches<S> make_batches() {
-    Batches<S> b{};
+template <class S, int VB>
+constexpr Batches<S, VB> make_batches() {
+    Batches<S, VB> b{};
     b.max_count = 0;
-    for (int B = 0; B < Batches<S>::NBATCH; ++B) {
+    for (int B = 0; B < Batches<S, VB>::NBATCH; ++B) {
         int n = 0;
-        for (int C = B * kVB; C < S::NB && C < (B + 1) * kVB; ++C) {
+        for (int C = B * VB; C < S::NB && C < (B + 1) * VB; ++C) {
             b.first[C] = n;
             n += S::T.col_deg[C];
         }
@@ -70,35 +74,38 @@ constexpr Batches<S> make_batches() {
     return b;
 }
 
-template <class S>
+template <class S, int L>
 struct BatchesOf {
-    static constexpr Batches<S> V = make_batches<S>();
+    static constexpr int VB = vb_of<L>();
+    static constexpr Batches<S, VB> V = make_batches<S, VB>();
 };
 
-template <class S, int FMT>
+template <class S, int FMT, int L>
 struct Lds {
-    static constexpr int XS = BatchesOf<S>::V.max_count;
-    float xq[XS][kL];             // per slot of a batch: message row
+    static constexpr int W = L / 64;
+    static constexpr int XS = BatchesOf<S, L>::V.max_count;
+    float xq[XS][L];              // per slot of a batch: message row
     // Per circulant row: bit R = XOR of the decisions of the variables that
     // check (R, row) meets, accumulated by the variable pass with LDS atomics.
-    uint32_t eacc[kL];
-    uint32_t unsat[2][2];         // per iteration parity, per wave: a violated check
+    uint32_t eacc[L];
+    uint32_t unsat[2][W];         // per iteration parity, per wave: a violated check
 };
 
 }  // namespace wreg2
 
-// Decodes one shot with the two waves of the calling workgroup (both waves
+// Decodes one shot with the L / 64 waves of the calling workgroup (every wave
 // must call it with the same, workgroup-uniform arguments): `syn` and `err`
 // point at the shot's syndrome and error words, priors, flags and the
 // a-posteriori output are indexed by `shot`.  Leaves with both waves at the
 // same iteration; the caller fences LDS before reusing `sh`.
-template <class S, int FMT, bool PER_BIT, bool POST>
+template <class S, int FMT, bool PER_BIT, bool POST, int L>
 __device__ __forceinline__ void wreg2_decode(const DecodeArgs &a, const DevCode *code, const long shot,
-                                             const uint32_t *syn, uint32_t *err_shot, wreg2::Lds<S, FMT> &sh) {
+                                             const uint32_t *syn, uint32_t *err_shot, wreg2::Lds<S, FMT, L> &sh) {
     using namespace wave;
-    using B = wreg2::BatchesOf<S>;
+    using B = wreg2::BatchesOf<S, L>;
     using prior_t = typename Fmt<FMT>::prior_t;
-    constexpr int L = wreg2::kL, MB = S::MB, NB = S::NB, DC = S::DC, N = NB * L;
+    static_assert(L == 128 || L == 256 || L == 512, "one wave per 64 circulant rows");
+    constexpr int MB = S::MB, NB = S::NB, DC = S::DC, N = NB * L, W = L / 64, VB = B::VB;
     constexpr int NBATCH = B::V.NBATCH;
 
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -172,8 +179,8 @@ __device__ __forceinline__ void wreg2_decode(const DecodeArgs &a, const DevCode 
         // ---------------- variable pass, a batch of columns at a time -------
         static_for<0, NBATCH>([&](auto Bc) {
             constexpr int b = decltype(Bc)::value;
-            constexpr int C0 = b * wreg2::kVB;
-            constexpr int C1 = (C0 + wreg2::kVB < NB) ? C0 + wreg2::kVB : NB;
+            constexpr int C0 = b * VB;
+            constexpr int C1 = (C0 + VB < NB) ? C0 + VB : NB;
             // 1. own messages of the batch's slots, at this lane's row
             static_for<C0, C1>([&](auto Cc) {
                 constexpr int C = decltype(Cc)::value;
@@ -259,19 +266,22 @@ __device__ __forceinline__ void wreg2_decode(const DecodeArgs &a, const DevCode 
         const uint64_t badmask = ballot(bad);
         if (t == 0) sh.unsat[k & 1][w] = badmask != 0 ? 1u : 0u;
         __syncthreads();
-        const bool conv = (__builtin_amdgcn_readfirstlane(sh.unsat[k & 1][0]) |
-                           __builtin_amdgcn_readfirstlane(sh.unsat[k & 1][1])) == 0;
+        uint32_t any = 0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) any |= __builtin_amdgcn_readfirstlane(sh.unsat[k & 1][i]);
+        const bool conv = any == 0;
         if ((a.early_stop && conv) || k == a.max_iters) {
-            // this wave's half of every column: words 4 C + 2 w, 4 C + 2 w + 1
-            // (a rolled loop from an opaque base: unrolled, the compiler would
-            // hoist 34 output addresses out of the iteration loop)
+            // this wave's rows of every column: words (L / 32) C + 2 w and
+            // (L / 32) C + 2 w + 1 (a rolled loop from an opaque base: unrolled,
+            // the compiler would hoist 34 output addresses out of the iteration
+            // loop)
             uint64_t eo = uniform64((uint64_t)(err_shot + 2 * w));
             asm volatile("" : "+s"(eo));
             uint32_t *err = (uint32_t *)eo;
 #pragma unroll 1
             for (int C = 0; C < NB; ++C) {
                 const uint64_t mc = ballot(((eb >> C) & 1ull) != 0);
-                if (t < 2) err[4 * C + t] = (uint32_t)(mc >> (32 * t));
+                if (t < 2) err[(L / 32) * C + t] = (uint32_t)(mc >> (32 * t));
             }
             if (threadIdx.x == 0) {
                 a.conv[shot] = conv ? 1 : 0;
@@ -289,29 +299,29 @@ __device__ __forceinline__ void wreg2_decode(const DecodeArgs &a, const DevCode 
     }
 }
 
-// One workgroup of two waves per shot; grid = batch.  Per-bit priors and the
-// a-posteriori output need more live registers than 168 (three waves per SIMD)
-// leave without spilling, so those variants run two waves per SIMD.
-template <class S, int FMT, bool PER_BIT, bool POST>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu((!PER_BIT && !POST) ? 3 : 2)))
+// One workgroup of L / 64 waves per shot; grid = batch.  Per-bit priors and
+// the a-posteriori output need more live registers than 168 (three waves per
+// SIMD) leave without spilling, so those variants run two waves per SIMD.
+template <class S, int FMT, bool PER_BIT, bool POST, int L>
+__global__ __launch_bounds__(L) __attribute__((amdgpu_waves_per_eu((!PER_BIT && !POST) ? 3 : 2)))
 void k_wreg2(const DecodeArgs a) {
-    constexpr int SW = S::MB * wreg2::kL / 32, EW = S::NB * wreg2::kL / 32;
-    __shared__ wreg2::Lds<S, FMT> sh;
+    constexpr int SW = S::MB * L / 32, EW = S::NB * L / 32;
+    __shared__ wreg2::Lds<S, FMT, L> sh;
     const long shot = xcd_wave_index(blockIdx.x, gridDim.x);
     if (shot >= a.batch) return;                                   // workgroup-uniform
     if (a.only && a.only[shot] == 0) return;                       // workgroup-uniform
-    wreg2_decode<S, FMT, PER_BIT, POST>(a, a.code, shot, a.syn + shot * SW, a.err + shot * EW, sh);
+    wreg2_decode<S, FMT, PER_BIT, POST, L>(a, a.code, shot, a.syn + shot * SW, a.err + shot * EW, sh);
 }
 
-template <class S, int FMT>
+template <class S, int FMT, int L>
 hipError_t launch_wreg2(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
-    const dim3 g((unsigned)a.batch), blk(128);
+    const dim3 g((unsigned)a.batch), blk(L);
     if (k.per_bit) {
-        if (k.post) hipLaunchKernelGGL((k_wreg2<S, FMT, true, true>), g, blk, 0, st, a);
-        else hipLaunchKernelGGL((k_wreg2<S, FMT, true, false>), g, blk, 0, st, a);
+        if (k.post) hipLaunchKernelGGL((k_wreg2<S, FMT, true, true, L>), g, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_wreg2<S, FMT, true, false, L>), g, blk, 0, st, a);
     } else {
-        if (k.post) hipLaunchKernelGGL((k_wreg2<S, FMT, false, true>), g, blk, 0, st, a);
-        else hipLaunchKernelGGL((k_wreg2<S, FMT, false, false>), g, blk, 0, st, a);
+        if (k.post) hipLaunchKernelGGL((k_wreg2<S, FMT, false, true, L>), g, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_wreg2<S, FMT, false, false, L>), g, blk, 0, st, a);
     }
     return hipGetLastError();
 }

@@ -20,6 +20,8 @@ hipError_t launch_wreg_L16(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wreg_L32(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wreg_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wreg2_L128(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_wreg2_L256(const LaunchKey &, const DecodeArgs &, hipStream_t);
+hipError_t launch_wreg2_L512(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wave_i16_L16(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wave_i16_L32(const LaunchKey &, const DecodeArgs &, hipStream_t);
 hipError_t launch_wave_i16_L64(const LaunchKey &, const DecodeArgs &, hipStream_t);
@@ -59,6 +61,8 @@ static hipError_t launch_decode_i16(const LaunchKey &k, const DecodeArgs &a, hip
             case 32: return launch_wreg_i16_L32(k, a, stream);
             case 64: return launch_wreg_i16_L64(k, a, stream);
             case 128: return launch_wreg2_L128(k, a, stream);
+            case 256: return launch_wreg2_L256(k, a, stream);
+            case 512: return launch_wreg2_L512(k, a, stream);
             default: break;
         }
     }
@@ -89,6 +93,8 @@ hipError_t launch_decode(const LaunchKey &k, const DecodeArgs &a, hipStream_t st
             case 32: return launch_wreg_L32(k, a, stream);
             case 64: return launch_wreg_L64(k, a, stream);
             case 128: return launch_wreg2_L128(k, a, stream);
+            case 256: return launch_wreg2_L256(k, a, stream);
+            case 512: return launch_wreg2_L512(k, a, stream);
             default: break;
         }
     }

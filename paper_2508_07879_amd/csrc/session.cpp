@@ -264,7 +264,7 @@ qldpc_status session_create_impl(qldpc_code code, qldpc_code code_x, const qldpc
     qldpc_status st = prepare_decode(code, &prm, max_batch, &k, &a);   // validates params
     if (st != QLDPC_OK) return st;
     if (k.layout == QLDPC_LAYOUT_HBM)
-        return set_error(QLDPC_ERR_UNSUPPORTED, "session_create: sessions keep messages on chip (L <= 128)");
+        return set_error(QLDPC_ERR_UNSUPPORTED, "session_create: sessions keep messages on chip (no HBM layout)");
     params = &prm;
     auto *s = new (std::nothrow) qldpc_session_s();
     if (!s) return set_error(QLDPC_ERR_OUT_OF_MEMORY, "session_create: host allocation");

@@ -1,0 +1,21 @@
+// Instantiations of the register-resident decoder with eight wavefronts per shot
+// for L = 512 (flooding; FP32, int8 and int16 messages; both block patterns).
+#include "decode_wreg2.h"
+
+namespace qldpc {
+
+hipError_t launch_wreg2_L512(const LaunchKey &k, const DecodeArgs &a, hipStream_t st) {
+    if (k.sched != 0 || k.L != 512) return hipErrorNotSupported;
+    if (k.which == 0) {
+        if (k.fmt == 0) return launch_wreg2<ShapeLP35Z, 0, 512>(k, a, st);
+        if (k.fmt == 1) return launch_wreg2<ShapeLP35Z, 1, 512>(k, a, st);
+        if (k.fmt == 2) return launch_wreg2<ShapeLP35Z, 2, 512>(k, a, st);
+    } else if (k.which == 1) {
+        if (k.fmt == 0) return launch_wreg2<ShapeLP35X, 0, 512>(k, a, st);
+        if (k.fmt == 1) return launch_wreg2<ShapeLP35X, 1, 512>(k, a, st);
+        if (k.fmt == 2) return launch_wreg2<ShapeLP35X, 2, 512>(k, a, st);
+    }
+    return hipErrorNotSupported;
+}
+
+}  // namespace qldpc

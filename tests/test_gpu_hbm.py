@@ -1,8 +1,7 @@
-"""Messages in device memory (QLDPC_LAYOUT_HBM) for lifts whose messages do
-not fit on chip (L = 256, 512), and for L = 128 where the on-chip layouts
-give the reference: same decisions, flags, iteration counts and posteriors
-as the oracle (FP32 within 1e-5, int8 bit-exact), the workspace contract,
-and the rejections."""
+"""Messages in device memory (QLDPC_LAYOUT_HBM, asked for explicitly) at
+L = 128, 256 and 512: same decisions, flags, iteration counts and
+posteriors as the oracle (FP32 within 1e-5, int8 bit-exact), the workspace
+contract, and the rejections."""
 import numpy as np
 import pytest
 
@@ -30,7 +29,7 @@ def side(L, which=0):
     return _sides[(L, which)]
 
 
-def case(L, shots, p, fmt=0, per_bit=False, which=0, seed=101, max_iters=32, early_stop=True, layout=0):
+def case(L, shots, p, fmt=0, per_bit=False, which=0, seed=101, max_iters=32, early_stop=True, layout=HBM):
     c, sd, H, dec = side(L, which)
     b = noise.Batch(sd, seed, np.arange(shots), p)
     if fmt == 0:
@@ -86,9 +85,12 @@ def test_L128_hbm_equals_lds_layout(fmt):
 def test_workspace_contract_and_rejections():
     c, sd, H, dec = side(256)
     B = 8
-    p32 = dec.params()
+    p32 = dec.params(layout=HBM)
     assert abi.qldpc_decode_workspace_bytes(dec.handle, p32, B) == B * 120 * 256 * 4
-    assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(fmt=abi.QLDPC_I8Q4), B) == B * 120 * 256
+    assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(fmt=abi.QLDPC_I8Q4, layout=HBM), B) == B * 120 * 256
+    # AUTO keeps the messages of every lift on chip (registers at L >= 256)
+    assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(), B) == 0
+    assert abi.qldpc_decode_workspace_bytes(side(512)[3].handle, side(512)[3].params(), B) == 0
     c64, sd64, _, dec64 = side(64)
     assert abi.qldpc_decode_workspace_bytes(dec64.handle, dec64.params(), B) == 0
     # L = 128: AUTO keeps messages on chip (8-wave workgroups, LDS); asked for
@@ -111,7 +113,8 @@ def test_workspace_contract_and_rejections():
     abi.qldpc_decode_batch_ws(dec.handle, p32, B, syn, pr, err, conv, it, None, ws, ws.numel())
     torch.cuda.synchronize()
     assert torch.all(conv == 1) and torch.all(err == 0)      # zero syndrome, positive priors
-    for bad in (dec.params(sched=abi.QLDPC_LAYERED), dec.params(layout=WAVE), dec.params(layout=abi.QLDPC_LAYOUT_BLOCK)):
+    for bad in (dec.params(sched=abi.QLDPC_LAYERED), dec.params(sched=abi.QLDPC_LAYERED, layout=HBM),
+                dec.params(layout=WAVE), dec.params(layout=abi.QLDPC_LAYOUT_BLOCK)):
         with pytest.raises(abi.QldpcError) as ei:
             abi.qldpc_decode_workspace_bytes(dec.handle, bad, B)
         assert ei.value.status == abi.QLDPC_ERR_UNSUPPORTED
@@ -127,7 +130,7 @@ def test_L256_large_batch_sampled():
     c, sd, H, dec = side(256)
     B = 16384
     b = noise.Batch(sd, 107, np.arange(B), 0.05)
-    e, conv, it, _ = gpu_decode(dec, b.s, b.gamma, posterior=False)
+    e, conv, it, _ = gpu_decode(dec, b.s, b.gamma, posterior=False, layout=HBM)
     ok = conv == 1
     assert ok.mean() > 0.5
     assert np.array_equal(noise.syndromes(sd, e[ok]), b.s[ok])

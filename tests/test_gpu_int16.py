@@ -142,7 +142,9 @@ def test_resident_session():
 
 def test_workspace_bytes_and_auto_layout():
     sd, H, dec = side(256)
-    assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(fmt=I16), 8) == 8 * 120 * 256 * 2
+    hbm = abi.QLDPC_LAYOUT_HBM
+    assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(fmt=I16, layout=hbm), 8) == 8 * 120 * 256 * 2
+    assert abi.qldpc_decode_workspace_bytes(dec.handle, dec.params(fmt=I16), 8) == 0     # AUTO: registers
     sd64, H64, dec64 = side(64)
     assert abi.qldpc_decode_workspace_bytes(dec64.handle, dec64.params(fmt=I16), 8) == 0
     case(64, 100, 0.05, 0, seed=329)                       # AUTO at L = 64

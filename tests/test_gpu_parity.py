@@ -243,8 +243,60 @@ def test_register_resident_L128_large_batch_sampled():
     assert np.array_equal(it[idx], o.iters)
 
 
+@pytest.mark.parametrize("L,fmt,per_bit", [(256, 0, False), (256, 1, False), (256, 2, False), (256, 0, True),
+                                             (256, 1, True), (512, 0, False), (512, 1, False), (512, 2, True)])
+def test_register_resident_large_lifts(L, fmt, per_bit):
+    """L = 256 and 512 with messages in registers: one workgroup of L / 64
+    wavefronts per shot.  Same decisions, flags, iterations and posteriors as
+    the oracle (FP32 within 1e-5, integer formats bit-exact), and identical
+    to the layout with messages in HBM."""
+    shots = 40 if L == 256 else 12
+    g, _ = run_case(L, shots, 0.05, fmt=fmt, per_bit=per_bit, seed=70 + L // 64 + fmt, layout=REG)
+    g_h, _ = run_case(L, shots, 0.05, fmt=fmt, per_bit=per_bit, seed=70 + L // 64 + fmt, layout=abi.QLDPC_LAYOUT_HBM)
+    for x, y in zip(g, g_h):
+        assert np.array_equal(x, y)
+
+
+def test_register_resident_large_lift_edge_cases():
+    run_case(256, 24, 0.05, max_iters=6, early_stop=False, seed=80, layout=REG)
+    g, _ = run_case(256, 9, 0.05, max_iters=1, seed=81, layout=REG)
+    assert np.all(g[2] == 1)
+    run_case(256, 16, 0.04, alpha=1.0, seed=82, layout=REG)
+    c, H, dec = code(256)
+    g, _ = run_case(256, 3, 0.03, syn=np.zeros((3, c.hz.m), np.uint8), seed=83, layout=REG)
+    assert np.all(g[1] == 1) and np.all(g[2] == 1)
+    for L in (256, 512):
+        c = lp.lp_code(L)
+        dx = Decoder(c.hx)
+        b = noise.Batch(c.hx, 84, np.arange(16 if L == 256 else 6), 0.05)
+        gx = gpu_decode(dx, b.s, b.gamma, layout=REG)
+        ox = oracle_decode(c.hx.dense(), b.s, b.gamma)
+        assert_parity(gx, ox, b.gamma[:, None], 0, tag=f"L={L} H_X register layout")
+
+
+def test_register_resident_L256_large_batch_sampled():
+    """8192 shots at p = 0.05 in one launch: every shot equals the HBM
+    layout's decode, converged shots reproduce their syndromes, and a sample
+    matches the oracle shot by shot."""
+    c, H, dec = code(256)
+    B = 8192
+    b = noise.Batch(c.hz, 1300, np.arange(B), 0.05)
+    g = gpu_decode(dec, b.s, b.gamma, posterior=False, layout=REG)
+    gh = gpu_decode(dec, b.s, b.gamma, posterior=False, layout=abi.QLDPC_LAYOUT_HBM)
+    for x, y in zip(g[:3], gh[:3]):
+        assert np.array_equal(x, y)
+    e, conv, it, _ = g
+    ok = conv == 1
+    assert ok.mean() > 0.5
+    assert np.array_equal(noise.syndromes(c.hz, e[ok]), b.s[ok])
+    idx = np.unique(np.concatenate([np.arange(0, B, 2048), [B - 1], np.nonzero(~ok)[0][:4]]))
+    o = oracle_decode(H, b.s[idx], b.gamma[idx])
+    assert np.array_equal(e[idx], o.e) and np.array_equal(conv[idx], o.converged)
+    assert np.array_equal(it[idx], o.iters)
+
+
 def test_register_resident_rejects_unsupported():
-    for L, fmt, sched in ((128, 0, 1), (128, 1, 1), (256, 0, 0)):
+    for L, fmt, sched in ((128, 0, 1), (128, 1, 1), (256, 0, 1), (512, 1, 1)):
         c, H, dec = code(L)
         p = dec.params(fmt=fmt, sched=sched, layout=REG)
         err, conv, it, _ = dec.outputs(2)

@@ -1,9 +1,10 @@
 """The allocation-free decode entry point (qldpc_decode_batch_static) against
 qldpc_decode_batch_ws on the same inputs.  Two calls in a row, the second
-with a smaller batch, in the HBM-message layout where the library's static
-workspace replaces the caller's (L = 256 in FP32 and int8, L = 128 with the
-layout asked for); the refusal of a batch beyond the static buffer; and an
-on-chip layout, which uses no workspace.  Outputs must be bit-identical:
+with a smaller batch, in the HBM-message layout (asked for explicitly), where
+the library's static workspace replaces the caller's (L = 256 in FP32 and
+int8, L = 128); the refusal of a batch beyond the static buffer; and the
+on-chip layouts AUTO takes (L = 64, and registers at L = 256), which use no
+workspace.  Outputs must be bit-identical:
 both entry points run the same kernels on the same inputs."""
 import numpy as np
 import pytest
@@ -61,7 +62,7 @@ def check_pair(L, prm, batches, p, fmt):
 @pytest.mark.parametrize("fmt,batches", [(abi.QLDPC_F32, (400, 97)), (abi.QLDPC_I8Q4, (1500, 33))])
 def test_static_equals_caller_workspace_L256(fmt, batches):
     dec = dec_for(256)
-    prm = dec.params(fmt=fmt)
+    prm = dec.params(fmt=fmt, layout=abi.QLDPC_LAYOUT_HBM)
     for B in batches:
         assert 0 < abi.qldpc_decode_workspace_bytes(dec.handle, prm, B) <= abi.QLDPC_STATIC_WORKSPACE_BYTES
     check_pair(256, prm, batches, 0.05, fmt)
@@ -74,7 +75,7 @@ def test_static_equals_caller_workspace_L128_hbm_layout():
 
 def test_static_refuses_beyond_its_buffer():
     dec = dec_for(256)
-    prm = dec.params()
+    prm = dec.params(layout=abi.QLDPC_LAYOUT_HBM)
     per_shot = 120 * 256 * 4
     B = abi.QLDPC_STATIC_WORKSPACE_BYTES // per_shot + 1
     syn = torch.zeros((B, dec.syn_words), dtype=torch.int32, device="cuda")
@@ -96,3 +97,6 @@ def test_static_on_chip_layout_needs_no_workspace():
     prm = dec.params()
     assert abi.qldpc_decode_workspace_bytes(dec.handle, prm, 4096) == 0
     check_pair(64, prm, (4096, 100), 0.03, abi.QLDPC_F32)
+    dec256 = dec_for(256)
+    assert abi.qldpc_decode_workspace_bytes(dec256.handle, dec256.params(), 4096) == 0
+    check_pair(256, dec256.params(), (600, 64), 0.05, abi.QLDPC_F32)
