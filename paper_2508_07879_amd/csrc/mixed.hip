@@ -20,11 +20,13 @@ struct qldpc_mixed_s {
     int32_t waves128 = 0;           // two-wave workgroups of the L = 128 grid
     bool has_grid[mix::kMixGrids] = {};   // (pattern, L) pairs among the plan's codes
     int32_t *scratch = nullptr;     // device
-    // The L = 128 grids run on a second stream, forked from and
-    // joined back into the caller's (or the capture) stream, so that they
-    // overlap the register grids instead of running before them.
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // The grids of each lift size run on a stream of their own, forked from
+    // and joined back into the caller's (or the capture) stream: captured,
+    // they become parallel graph branches, so a grid's tail is filled by the
+    // waves of the others instead of the next grid waiting for it.
+    static constexpr int kBranches = 4;   // lifts 128, 64, 32, 16
+    hipStream_t side[kBranches] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kBranches] = {};
     std::mutex mu;
     std::map<std::tuple<int32_t, const void *, const void *, const void *, const void *, const void *, const void *,
                         const void *, const void *, const void *, void *, int32_t>,
@@ -71,30 +73,46 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
     hipLaunchKernelGGL(k_mix_count, dim3(nb), dim3(kBucketThreads), 0, st, m);
     hipLaunchKernelGGL(k_mix_plan, dim3(1), dim3(64), 0, st, m);
     hipLaunchKernelGGL(k_mix_scatter, dim3(nb), dim3(kBucketThreads), 0, st, m);
-    // one persistent grid per (pattern, lift size) present, largest L first;
-    // the L = 128 grids on the side stream, overlapping the others
+    // one persistent grid per (pattern, lift size) present, largest L first,
+    // each lift size on its own branch when there are several
     const unsigned w64 = (unsigned)waves, w128 = (unsigned)x->waves128;
     const bool *g = x->has_grid;
-    const dim3 hb(128);
-    const bool fork = (g[3] || g[7]) && (g[0] || g[1] || g[2] || g[4] || g[5] || g[6]);
-    hipStream_t bs = st;
+    const bool lift[qldpc_mixed_s::kBranches] = {g[3] || g[7], g[2] || g[6], g[1] || g[5], g[0] || g[4]};
+    const int nlift = (int)lift[0] + (int)lift[1] + (int)lift[2] + (int)lift[3];
+    const bool fork = nlift > 1;
     hipError_t fe = hipSuccess;
-    if (fork) {
-        fe = hipEventRecord(x->ev_fork, st);
-        if (fe == hipSuccess) fe = hipStreamWaitEvent(x->side, x->ev_fork, 0);
-        if (fe != hipSuccess) return hip_error(fe, "mixed_decode: fork");
-        bs = x->side;
+    if (fork && (fe = hipEventRecord(x->ev_fork, st)) != hipSuccess) return hip_error(fe, "mixed_decode: fork");
+    for (int b = 0; b < qldpc_mixed_s::kBranches; ++b) {
+        if (!lift[b]) continue;
+        hipStream_t bs = st;
+        if (fork) {
+            if ((fe = hipStreamWaitEvent(x->side[b], x->ev_fork, 0)) != hipSuccess)
+                return hip_error(fe, "mixed_decode: fork");
+            bs = x->side[b];
+        }
+        switch (b) {
+            case 0:
+                if (g[3]) hipLaunchKernelGGL((k_mix_wreg2<ShapeLP35Z>), dim3(w128), dim3(128), 0, bs, m);
+                if (g[7]) hipLaunchKernelGGL((k_mix_wreg2<ShapeLP35X>), dim3(w128), dim3(128), 0, bs, m);
+                break;
+            case 1:
+                if (g[2]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 64>), dim3(w64), dim3(64), 0, bs, m);
+                if (g[6]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 64>), dim3(w64), dim3(64), 0, bs, m);
+                break;
+            case 2:
+                if (g[1]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 32>), dim3(w64), dim3(64), 0, bs, m);
+                if (g[5]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 32>), dim3(w64), dim3(64), 0, bs, m);
+                break;
+            default:
+                if (g[0]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 16>), dim3(w64), dim3(64), 0, bs, m);
+                if (g[4]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 16>), dim3(w64), dim3(64), 0, bs, m);
+                break;
+        }
+        if (fork) {
+            if ((fe = hipEventRecord(x->ev_join[b], x->side[b])) != hipSuccess) return hip_error(fe, "mixed_decode: join");
+            if ((fe = hipStreamWaitEvent(st, x->ev_join[b], 0)) != hipSuccess) return hip_error(fe, "mixed_decode: join");
+        }
     }
-    if (g[3]) hipLaunchKernelGGL((k_mix_wreg2<ShapeLP35Z>), dim3(w128), hb, 0, bs, m);
-    if (g[7]) hipLaunchKernelGGL((k_mix_wreg2<ShapeLP35X>), dim3(w128), hb, 0, bs, m);
-    if (fork && (fe = hipEventRecord(x->ev_join, x->side)) != hipSuccess) return hip_error(fe, "mixed_decode: join");
-    if (g[2]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 64>), dim3(w64), dim3(64), 0, st, m);
-    if (g[6]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 64>), dim3(w64), dim3(64), 0, st, m);
-    if (g[1]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 32>), dim3(w64), dim3(64), 0, st, m);
-    if (g[5]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 32>), dim3(w64), dim3(64), 0, st, m);
-    if (g[0]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35Z, 16>), dim3(w64), dim3(64), 0, st, m);
-    if (g[4]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 16>), dim3(w64), dim3(64), 0, st, m);
-    if (fork && (fe = hipStreamWaitEvent(st, x->ev_join, 0)) != hipSuccess) return hip_error(fe, "mixed_decode: join");
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "mixed_decode: launch");
     return QLDPC_OK;
@@ -139,14 +157,18 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
     }
     hipError_t e = hipSetDevice(x->device);
     if (e == hipSuccess) e = hipMalloc(&x->scratch, sizeof(int32_t) * (mix::kScratchHead + (size_t)max_batch));
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&x->side, hipStreamNonBlocking);
+    for (int b = 0; b < qldpc_mixed_s::kBranches && e == hipSuccess; ++b) {
+        e = hipStreamCreateWithFlags(&x->side[b], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&x->ev_join[b], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&x->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (x->scratch) (void)hipFree(x->scratch);
-        if (x->side) (void)hipStreamDestroy(x->side);
+        for (int b = 0; b < qldpc_mixed_s::kBranches; ++b) {
+            if (x->side[b]) (void)hipStreamDestroy(x->side[b]);
+            if (x->ev_join[b]) (void)hipEventDestroy(x->ev_join[b]);
+        }
         if (x->ev_fork) (void)hipEventDestroy(x->ev_fork);
-        if (x->ev_join) (void)hipEventDestroy(x->ev_join);
         delete x;
         return set_error(QLDPC_ERR_OUT_OF_MEMORY, "mixed_create: scratch, stream or event allocation");
     }
@@ -157,11 +179,14 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
 qldpc_status qldpc_mixed_destroy(qldpc_mixed x) {
     if (!x) return QLDPC_OK;
     for (auto &kv : x->graphs) (void)hipGraphExecDestroy(kv.second);
-    if (x->side) (void)hipStreamSynchronize(x->side);
+    for (int b = 0; b < qldpc_mixed_s::kBranches; ++b)
+        if (x->side[b]) (void)hipStreamSynchronize(x->side[b]);
     if (x->scratch) (void)hipFree(x->scratch);
-    if (x->side) (void)hipStreamDestroy(x->side);
+    for (int b = 0; b < qldpc_mixed_s::kBranches; ++b) {
+        if (x->side[b]) (void)hipStreamDestroy(x->side[b]);
+        if (x->ev_join[b]) (void)hipEventDestroy(x->ev_join[b]);
+    }
     if (x->ev_fork) (void)hipEventDestroy(x->ev_fork);
-    if (x->ev_join) (void)hipEventDestroy(x->ev_join);
     delete x;
     return QLDPC_OK;
 }
