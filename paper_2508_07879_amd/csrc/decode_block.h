@@ -354,8 +354,16 @@ __device__ __forceinline__ void block_decode(const DecodeArgs &a, const DevCode 
     });
 }
 
+// Waves per SIMD the throughput kernel asks the register allocator for: an
+// 8-wave workgroup with integer messages needs at most half of LDS per
+// compute unit, so three workgroups fit if each wave stays within 80 VGPRs
+// (the per-edge addresses the loop keeps otherwise take it to 133).
+template <int L, int FMT, int NW>
+constexpr int block_waves() { return (NW == 8 && FMT != 0) ? 4 : 1; }
+
 template <class S, int L, int FMT, int NW, bool PER_BIT, bool POST>
-__global__ __launch_bounds__(64 * NW) void k_block(const DecodeArgs a) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(block_waves<L, FMT, NW>())))
+void k_block(const DecodeArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[BlockLds<S, L, FMT, NW>::bytes];
     const long shot = blockIdx.x;
     if (a.only && a.only[shot] == 0) return;   // uniform over the workgroup

@@ -96,7 +96,7 @@ struct Lds {
 // Decodes one shot with the L / 64 waves of the calling workgroup (every wave
 // must call it with the same, workgroup-uniform arguments): `syn` and `err`
 // point at the shot's syndrome and error words, priors, flags and the
-// a-posteriori output are indexed by `shot`.  Leaves with both waves at the
+// a-posteriori output are indexed by `shot`.  Leaves with every wave at the
 // same iteration; the caller fences LDS before reusing `sh`.
 template <class S, int FMT, bool PER_BIT, bool POST, int L>
 __device__ __forceinline__ void wreg2_decode(const DecodeArgs &a, const DevCode *code, const long shot,

@@ -20,11 +20,15 @@ struct qldpc_mixed_s {
     int32_t waves128 = 0;           // two-wave workgroups of the L = 128 grid
     bool has_grid[mix::kMixGrids] = {};   // (pattern, L) pairs among the plan's codes
     int32_t *scratch = nullptr;     // device
-    // The grids of each lift size run on a stream of their own, forked from
-    // and joined back into the caller's (or the capture) stream: captured,
-    // they become parallel graph branches, so a grid's tail is filled by the
-    // waves of the others instead of the next grid waiting for it.
+    // Captured plans run the grids of each lift size on a stream of their
+    // own, forked from and joined back into the capture stream: they become
+    // parallel graph branches, so a grid's tail is filled by the waves of the
+    // others instead of the next grid waiting for it.  Eager plans (several
+    // of which a server runs at once, one per slot, on a few hardware
+    // queues) use one side stream for the L = 128 grids and run the others
+    // one after the other on the caller's stream.
     static constexpr int kBranches = 4;   // lifts 128, 64, 32, 16
+    int nside() const { return use_graph ? kBranches : 1; }
     hipStream_t side[kBranches] = {};
     hipEvent_t ev_fork = nullptr, ev_join[kBranches] = {};
     std::mutex mu;
@@ -79,13 +83,14 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
     const bool *g = x->has_grid;
     const bool lift[qldpc_mixed_s::kBranches] = {g[3] || g[7], g[2] || g[6], g[1] || g[5], g[0] || g[4]};
     const int nlift = (int)lift[0] + (int)lift[1] + (int)lift[2] + (int)lift[3];
-    const bool fork = nlift > 1;
+    const bool fork = nlift > 1 && (x->use_graph || lift[0]);
     hipError_t fe = hipSuccess;
     if (fork && (fe = hipEventRecord(x->ev_fork, st)) != hipSuccess) return hip_error(fe, "mixed_decode: fork");
     for (int b = 0; b < qldpc_mixed_s::kBranches; ++b) {
         if (!lift[b]) continue;
+        const bool own = fork && b < x->nside();   // this lift on a side stream
         hipStream_t bs = st;
-        if (fork) {
+        if (own) {
             if ((fe = hipStreamWaitEvent(x->side[b], x->ev_fork, 0)) != hipSuccess)
                 return hip_error(fe, "mixed_decode: fork");
             bs = x->side[b];
@@ -108,11 +113,14 @@ qldpc_status enqueue(qldpc_mixed x, int32_t batch, const int32_t *shot_code, con
                 if (g[4]) hipLaunchKernelGGL((k_mix_decode<ShapeLP35X, 16>), dim3(w64), dim3(64), 0, bs, m);
                 break;
         }
-        if (fork) {
-            if ((fe = hipEventRecord(x->ev_join[b], x->side[b])) != hipSuccess) return hip_error(fe, "mixed_decode: join");
-            if ((fe = hipStreamWaitEvent(st, x->ev_join[b], 0)) != hipSuccess) return hip_error(fe, "mixed_decode: join");
-        }
+        if (own && (fe = hipEventRecord(x->ev_join[b], x->side[b])) != hipSuccess)
+            return hip_error(fe, "mixed_decode: join");
     }
+    // the caller's stream waits for the side branches only after its own
+    // grids are enqueued, so those run beside them
+    for (int b = 0; b < qldpc_mixed_s::kBranches; ++b)
+        if (lift[b] && fork && b < x->nside() && (fe = hipStreamWaitEvent(st, x->ev_join[b], 0)) != hipSuccess)
+            return hip_error(fe, "mixed_decode: join");
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "mixed_decode: launch");
     return QLDPC_OK;
@@ -157,7 +165,7 @@ qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const q
     }
     hipError_t e = hipSetDevice(x->device);
     if (e == hipSuccess) e = hipMalloc(&x->scratch, sizeof(int32_t) * (mix::kScratchHead + (size_t)max_batch));
-    for (int b = 0; b < qldpc_mixed_s::kBranches && e == hipSuccess; ++b) {
+    for (int b = 0; b < x->nside() && e == hipSuccess; ++b) {
         e = hipStreamCreateWithFlags(&x->side[b], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&x->ev_join[b], hipEventDisableTiming);
     }
