@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--L", type=int, default=64)
-    ap.add_argument("--cpu-shots", type=int, default=8192, help="oracle sample per noise rate")
+    ap.add_argument("--cpu-shots", type=int, default=16384, help="oracle sample per noise rate")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--latency-reqs", type=int, default=100000, help="requests per noise rate (0 = skip)")
