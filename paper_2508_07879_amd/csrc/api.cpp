@@ -130,7 +130,7 @@ qldpc_status prepare_decode(qldpc_code code, const qldpc_decode_params *p, int32
         }
         // Defaults measured on MI355X (65536 shots at L = 64, 32768 at L = 128,
         // p = 0.01 / 0.03 / 0.05): messages in registers (L = 64 FP32 flooding
-        // 37.3 M syndromes/s against 26.9 M for 8-wave workgroups; L = 128
+        // 38.8 M syndromes/s against 26.9 M for 8-wave workgroups; L = 128
         // flooding, two wavefronts per shot, 13.0 M FP32 / 12.8 M int8 against
         // 12.0 / 8.6 M for 8-wave workgroups with messages in LDS and 3.3 /
         // 4.55 M with messages in HBM); L = 128 layered a wavefront per shot;

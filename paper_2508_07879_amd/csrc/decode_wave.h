@@ -587,6 +587,12 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
 #pragma unroll
         for (int h = 0; h < H; ++h) eb[h] = 0;
 
+        // REG: the wave's priority is raised for the variable pass (cross-lane
+        // permutes and their dependent sums) and lowered for the check pass
+        // (registers only), so a wave's permutes issue ahead of the other
+        // waves' register work, which then fills the wait (37.1 -> 38.2-38.7 M
+        // syndromes/s at L = 64; 23.0 -> 24.1 M with 16 fixed iterations).
+        if constexpr (REG) __builtin_amdgcn_s_setprio(0);
         if constexpr (SCHED == 0) {
             // ---------------- check-node pass --------------------------------
 #pragma unroll
@@ -713,6 +719,7 @@ __device__ __forceinline__ void wave_decode(const DecodeArgs &a, const DevCode *
         }
 
         if constexpr (REG) seed_acc();
+        if constexpr (REG) __builtin_amdgcn_s_setprio(2);
         // ---------------- variable nodes, a posteriori, decision -------------
         // Block columns are processed Knobs::vn_batch at a time: every message
         // of the batch is loaded before any is overwritten, so the rotated
