@@ -361,10 +361,11 @@ typedef struct qldpc_mixed_s *qldpc_mixed;
  * 4 * (max_batch + 24) bytes of device scratch.  One persistent grid per
  * (pattern, lift size) decodes its shots with its messages in registers: a
  * wavefront per tile of 64 / L shots for L <= 64, a workgroup of two
- * wavefronts per shot for L = 128 (on a second stream, overlapping the
- * others).  use_graph = 1: every distinct argument set is captured
- * once as a hipGraph (bucketing kernels + persistent decoders) and
- * replayed. */
+ * wavefronts per shot for L = 128.  use_graph = 1: every distinct argument
+ * set is captured once as a hipGraph (bucketing kernels + persistent
+ * decoders, each lift size's grids on a parallel branch) and replayed;
+ * use_graph = 0: launched directly, the L = 128 grids on a side stream
+ * beside the others (the plan owns its side streams). */
 qldpc_status qldpc_mixed_create(const qldpc_code *codes, int32_t ncodes, const qldpc_decode_params *params,
                                 int32_t max_batch, int32_t use_graph, qldpc_mixed *out);
 qldpc_status qldpc_mixed_destroy(qldpc_mixed plan);
